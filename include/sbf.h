@@ -1,0 +1,153 @@
+/*
+ * sbf.h - C ABI of an MI355X (gfx950) Super Bloom filter for DNA k-mers.
+ *
+ * The filter is the sequence-native Super Bloom filter of "cuSBF: A
+ * Minimizer-Aware Bloom Filter for Genomic Sequence Data on Modern GPUs":
+ * every k-mer of a DNA sequence is sent to the shard picked by the low bits
+ * of its minimizer hash (Section "Minimizers and Super-k-mers", Algorithm 1),
+ * and inside that shard it is represented by its k-s+1 overlapping s-mers,
+ * H bits each (Section "Findere Scheme").  A query answers 1 only when every
+ * bit of every s-mer is set (Algorithm 2, Contains).
+ *
+ * Data layout (Section "Data Layout"): the filter owns one device array of
+ * N = 2^P shards, N = next power of two of ceil(bits / 256), at least 1.
+ * Shard i is the four 64-bit words at index 4i .. 4i+3; hash index t of an
+ * s-mer sets one bit of word t mod 4.  Bit b of word w is (w >> b) & 1.  The
+ * array starts zeroed.
+ *
+ * Alphabet: A/a=0, C/c=1, G/g=2, T/t=3; every other byte (N, separators,
+ * padding) is invalid and no k-mer containing it is inserted; such k-mers
+ * answer 0.  k-mers are read on the forward strand only.
+ *
+ * Conventions for every call:
+ *   - A function returning int returns SBF_OK (0) or a negative SBF_E_*
+ *     code, and records a message readable with sbf_last_error() on the
+ *     calling thread.  No C++ exception crosses this boundary.
+ *   - "Host" entry points take host pointers, run on the filter's own HIP
+ *     stream and synchronise before returning (Section "Library Design").
+ *   - "_dev" entry points take device pointers and a hipStream_t passed as
+ *     void* (NULL = the filter's own stream); they are stream-ordered and do
+ *     not synchronise.  The caller keeps the buffers alive until the work on
+ *     that stream has finished.
+ *   - The caller owns every sequence, offset and output buffer it passes; the
+ *     library owns the filter's device array and its internal staging
+ *     buffers.  A filter is used by one host thread at a time.
+ */
+#ifndef SBF_H
+#define SBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBF_OK 0
+#define SBF_E_INVAL (-1)  /* bad argument: parameters, NULL pointer, size */
+#define SBF_E_NOMEM (-2)  /* a device or host allocation failed */
+#define SBF_E_DEVICE (-3) /* a HIP call or kernel launch failed */
+
+/* Kernel families (sbf_set_variant). */
+#define SBF_VARIANT_AUTO 0    /* rolling kernel when compiled for (k,s,m,H), else generic */
+#define SBF_VARIANT_ROLLING 1 /* super-k-mer rolling kernels (specialised parameter sets) */
+#define SBF_VARIANT_GENERIC 2 /* one k-mer per lane, run-time k, s, m, H */
+
+typedef struct sbf_filter sbf_filter; /* opaque; owns its device bit array */
+
+/* Create a filter (Section "Library Design": k, s, m and H configure the
+ * filter; the total size in bits fixes the shard count).
+ *   k: k-mer length, 1 <= k <= 32 (a k-mer packs into 64 bits).
+ *   s: Findere s-mer length, 1 <= s <= k (k-s+1 s-mers per k-mer).
+ *   m: minimizer length, 1 <= m <= k (k-m+1 m-mers per k-mer).
+ *   H: bits per s-mer, 1 <= H <= 16; hash index t uses word t mod 4.
+ *   bits: requested size, 1 <= bits <= 2^40; rounded up to 256 * 2^P.
+ * Allocates and zeroes the device array on the current HIP device.
+ * Returns NULL on error (SBF_E_INVAL for bad parameters, SBF_E_NOMEM when the
+ * device allocation fails, SBF_E_DEVICE otherwise); nothing is left allocated
+ * on failure. */
+sbf_filter *sbf_create(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits);
+
+/* Free the filter and its device memory after waiting for its stream.
+ * sbf_destroy(NULL) does nothing. */
+void sbf_destroy(sbf_filter *f);
+
+/* Insert every valid k-mer of seq[0 .. len) (Algorithm 1).  Host pointer,
+ * synchronous.  len < k inserts nothing and returns SBF_OK.  Repeated inserts
+ * accumulate by OR. */
+int sbf_insert_seq(sbf_filter *f, const char *seq, uint64_t len);
+
+/* Query every k-mer of seq[0 .. len) (Algorithm 2).  out[i] (0 or 1) answers
+ * the k-mer starting at seq[i], for i < len-k+1; invalid k-mers give 0.
+ * Host pointers, synchronous.  len < k writes nothing.  The filter is not
+ * modified. */
+int sbf_query_seq(sbf_filter *f, const char *seq, uint64_t len, uint8_t *out);
+
+/* Code and message of the last error on the calling thread (SBF_OK and ""
+ * when the last call succeeded).  msg may be NULL.  The string stays valid
+ * until the next call into the library on this thread. */
+int sbf_last_error(const char **msg);
+
+/* Geometry: number of shards N, filter size in bits (256 * N) and number of
+ * 64-bit words (4 * N).  0 for a NULL filter. */
+uint64_t sbf_num_shards(const sbf_filter *f);
+uint64_t sbf_num_bits(const sbf_filter *f);
+uint64_t sbf_num_words(const sbf_filter *f);
+
+/* Copy the whole bit array to host_dst (nwords must equal sbf_num_words), or
+ * overwrite it from host_src.  Both wait for all work on the device first.
+ * Together with the parameters this is the full state of the filter, so
+ * get + create + set restores it bit for bit. */
+int sbf_get_bits(const sbf_filter *f, uint64_t *host_dst, uint64_t nwords);
+int sbf_set_bits(sbf_filter *f, const uint64_t *host_src, uint64_t nwords);
+
+/* Zero the bit array, ordered on stream (NULL = the filter's stream); does
+ * not synchronise. */
+int sbf_clear(sbf_filter *f, void *stream);
+
+/* Device pointer of the bit array (4 * N words).  Valid until sbf_destroy. */
+const uint64_t *sbf_device_words(const sbf_filter *f);
+
+/* Stream-ordered forms of sbf_insert_seq / sbf_query_seq on device memory
+ * (Section "Library Design": device-facing entry points leave ordering to the
+ * caller).  d_out has room for len-k+1 bytes. */
+int sbf_insert_seq_dev(sbf_filter *f, const char *d_seq, uint64_t len, void *stream);
+int sbf_query_seq_dev(sbf_filter *f, const char *d_seq, uint64_t len, uint8_t *d_out,
+                      void *stream);
+
+/* Record batches (Section "Sequence-Native Design": records are concatenated
+ * and no k-mer spans two records).  Record r is seq[off[r] .. off[r+1]);
+ * off has nrec+1 non-decreasing entries with off[0] = 0.  Queries write one
+ * byte per base position, out[0 .. off[nrec]): out[off[r]+i] answers k-mer i
+ * of record r; the last k-1 positions of each record, and every position of
+ * a record shorter than k, are 0.
+ * Host form: host pointers, validated, synchronous. */
+int sbf_insert_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec);
+int sbf_query_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec,
+                    uint8_t *out);
+
+/* Device form: d_seq holds len = off[nrec] bases, d_off is a device array of
+ * nrec+1 offsets (not read by the host, so it is not validated: off[0] must
+ * be 0 and off[nrec] must equal len).  Stream-ordered.  The library keeps one
+ * scratch buffer of len/8 bytes per stream used (record starts as bits);
+ * calls on different streams may overlap. */
+int sbf_insert_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
+                         uint64_t nrec, void *stream);
+int sbf_query_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
+                        uint64_t nrec, uint8_t *d_out, void *stream);
+
+/* Choose the kernel family (SBF_VARIANT_*).  SBF_VARIANT_ROLLING fails with
+ * SBF_E_INVAL when no rolling kernel is compiled for the filter's (k,s,m,H).
+ * Both families give bit-identical filters and answers. */
+int sbf_set_variant(sbf_filter *f, int variant);
+int sbf_get_variant(const sbf_filter *f); /* the family in effect (1 or 2) */
+
+/* Bytes of sequence the host entry points stage on the device per chunk
+ * (default 256 MiB; at least 4096).  Inputs longer than this are processed in
+ * chunks that overlap by k-1 bases. */
+int sbf_set_staging_bytes(sbf_filter *f, uint64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBF_H */

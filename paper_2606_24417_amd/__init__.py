@@ -1,0 +1,10 @@
+"""MI355X (gfx950) Super Bloom filter for DNA k-mers: the sequence-native
+insert and query path (2-bit encoding, rolling minimizer and s-mer hashing,
+super-k-mer sharding, atomic-OR insert, leader-load query) behind the C ABI
+of include/sbf.h, with a thin ctypes binding."""
+
+from .sbf import (SBF_E_DEVICE, SBF_E_INVAL, SBF_E_NOMEM, SBF_OK, VARIANT_AUTO, VARIANT_GENERIC,
+                  VARIANT_ROLLING, Filter, SBFError, last_error, lib)
+
+__all__ = ["Filter", "SBFError", "lib", "last_error", "SBF_OK", "SBF_E_INVAL", "SBF_E_NOMEM", "SBF_E_DEVICE",
+           "VARIANT_AUTO", "VARIANT_ROLLING", "VARIANT_GENERIC"]

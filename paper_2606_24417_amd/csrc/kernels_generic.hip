@@ -1,0 +1,254 @@
+// Generic insert and query kernels: one k-mer per lane, k, s, m and H known
+// only at run time (any 1 <= m, s <= k <= 32, 1 <= H <= 16).  This is the
+// paper's per-k-mer scheme (Algorithms 1 and 2) written for wave64:
+//   insert: each lane packs its k-mer, takes the minimum m-mer hash, ORs the
+//   bits of its k-s+1 s-mers into per-word masks; lanes with equal shard in a
+//   contiguous run of the wave merge their masks with a segmented OR scan
+//   (ds_bpermute shifts of 1, 2, 4, .., 32 lanes) and the run's last lane
+//   issues the atomics;
+//   query: each lane loads its shard and tests every bit.
+// Also the small utility kernels of the library.
+#include "sbf_device.h"
+#include "sbf_internal.h"
+
+namespace sbf {
+namespace {
+
+constexpr int kGenericWG = 256;
+constexpr int kGenericRounds = 4;                         // k-mers per lane
+constexpr int kGenericTile = kGenericWG * kGenericRounds;  // k-mers per workgroup
+constexpr int kGenericGran = kGenericTile / 16 + 4;
+
+struct RtParams {
+  int k, s, m, H;
+  uint64_t shard_mask;
+};
+
+// k-mer starting at tile position q (packed, first base most significant)
+// and its validity.
+__device__ __forceinline__ bool load_kmer(const uint32_t *s_codes, const uint32_t *s_vb, int q, int k,
+                                          uint64_t &kmer) {
+  const int g = q >> 4;
+  const int sh = (q & 15) * 2;
+  const uint32_t a0 = s_codes[g], a1 = s_codes[g + 1], a2 = s_codes[g + 2];
+  const uint32_t hi = sh ? __builtin_amdgcn_alignbit(a0, a1, 32 - sh) : a0;
+  const uint32_t lo = sh ? __builtin_amdgcn_alignbit(a1, a2, 32 - sh) : a1;
+  const uint64_t win = ((uint64_t)hi << 32) | lo;
+  kmer = k == 32 ? win : (win >> (64 - 2 * k));
+  uint64_t vbits = 0, sbits = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t vb = s_vb[g + i];
+    vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
+    sbits |= (uint64_t)(vb >> 16) << (16 * i);
+  }
+  vbits >>= (q & 15);
+  sbits >>= (q & 15);
+  const uint64_t kmask = k == 64 ? ~0ull : ((1ull << k) - 1ull);
+  const bool all_valid = (vbits & kmask) == kmask;
+  const bool no_start = ((sbits >> 1) & (kmask >> 1)) == 0;
+  return all_valid && no_start;
+}
+
+__device__ __forceinline__ uint64_t sub_window(uint64_t kmer, int k, int L, int j) {
+  const uint64_t x = kmer >> (2 * (k - L - j));
+  return L == 32 ? x : (x & ((1ull << (2 * L)) - 1ull));
+}
+
+__device__ __forceinline__ uint64_t min_hash(uint64_t kmer, const RtParams &p) {
+  uint64_t best = ~0ull;
+  for (int j = 0; j + p.m <= p.k; ++j) best = umin64(best, minimizer_hash(sub_window(kmer, p.k, p.m, j)));
+  return best;
+}
+
+template <int SW>
+__device__ __forceinline__ void kmer_masks(uint64_t kmer, const RtParams &p, uint64_t (&msk)[SW]) {
+#pragma unroll
+  for (int w = 0; w < SW; ++w) msk[w] = 0;
+  const int W = 64 / p.H;
+  for (int j = 0; j + p.s <= p.k; ++j) {
+    const uint64_t g = smer_hash(sub_window(kmer, p.k, p.s, j));
+    for (int t = 0; t < p.H; ++t) {
+      const uint64_t bit = 1ull << bit_address_rt(g, t, p.H);
+      int word = t & 3;
+      if (SW > 4) word += 4 * (int)((g >> (t * W + 6)) & (uint64_t)(SW / 4 - 1));
+#pragma unroll
+      for (int w = 0; w < SW; ++w) msk[w] |= (word == w) ? bit : 0ull;
+    }
+  }
+}
+
+template <int SW>
+__global__ __launch_bounds__(kGenericWG) void insert_generic_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+                                                                    const uint32_t *__restrict__ starts,
+                                                                    int aligned16, uint64_t *__restrict__ words,
+                                                                    RtParams p) {
+  __shared__ uint32_t s_codes[kGenericGran];
+  __shared__ uint32_t s_vb[kGenericGran];
+  const uint64_t base = (uint64_t)blockIdx.x * kGenericTile;
+  stage_granules<kGenericWG>(seq, len, base, starts, aligned16 != 0, kGenericGran, s_codes, s_vb);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int round = 0; round < kGenericRounds; ++round) {
+    const int q = round * kGenericWG + threadIdx.x;
+    uint64_t kmer;
+    const bool v = load_kmer(s_codes, s_vb, q, p.k, kmer);
+    uint64_t shard = 0;
+    uint64_t msk[SW];
+    if (v) {
+      shard = min_hash(kmer, p) & p.shard_mask;
+      kmer_masks<SW>(kmer, p, msk);
+    } else {
+#pragma unroll
+      for (int w = 0; w < SW; ++w) msk[w] = 0;
+    }
+    // run heads: first lane, or previous lane invalid or in another shard
+    const uint64_t prev_shard = __shfl_up(shard, 1);
+    const int prev_v = __shfl_up((int)v, 1);
+    const bool head = v && (lane == 0 || !prev_v || prev_shard != shard);
+    // segmented inclusive OR scan towards higher lanes; a run ends at a lane
+    // whose successor starts a new run (or is invalid)
+    bool stop = head || !v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int ostop = __shfl_up((int)stop, d);
+      uint64_t o[SW];
+#pragma unroll
+      for (int w = 0; w < SW; ++w) o[w] = __shfl_up(msk[w], d);
+      if (lane >= d && !stop) {
+#pragma unroll
+        for (int w = 0; w < SW; ++w) msk[w] |= o[w];
+        stop = ostop != 0;
+      }
+    }
+    const int next_begins = __shfl_down((int)(head || !v), 1);
+    const bool tail = v && (lane == 63 || next_begins);
+    if (tail) {
+      uint64_t *dst = words + shard * (uint64_t)SW;
+#pragma unroll
+      for (int w = 0; w < SW; ++w)
+        if (msk[w]) atomic_or64(dst + w, msk[w]);
+    }
+  }
+}
+
+template <int SW>
+__global__ __launch_bounds__(kGenericWG) void query_generic_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+                                                                   const uint32_t *__restrict__ starts,
+                                                                   int aligned16,
+                                                                   const uint64_t *__restrict__ words, RtParams p,
+                                                                   uint8_t *__restrict__ out, uint64_t n_out) {
+  __shared__ uint32_t s_codes[kGenericGran];
+  __shared__ uint32_t s_vb[kGenericGran];
+  const uint64_t base = (uint64_t)blockIdx.x * kGenericTile;
+  stage_granules<kGenericWG>(seq, len, base, starts, aligned16 != 0, kGenericGran, s_codes, s_vb);
+  __syncthreads();
+  for (int round = 0; round < kGenericRounds; ++round) {
+    const int q = round * kGenericWG + threadIdx.x;
+    const uint64_t pos = base + (uint64_t)q;
+    uint64_t kmer;
+    const bool v = load_kmer(s_codes, s_vb, q, p.k, kmer);
+    uint8_t present = 0;
+    if (v) {
+      const uint64_t shard = min_hash(kmer, p) & p.shard_mask;
+      uint64_t msk[SW];
+      kmer_masks<SW>(kmer, p, msk);
+      const uint64_t *src = words + shard * (uint64_t)SW;
+      bool all = true;
+#pragma unroll
+      for (int w = 0; w < SW; ++w) all = all && ((src[w] & msk[w]) == msk[w]);
+      present = all ? 1 : 0;
+    }
+    if (pos < n_out) out[pos] = present;
+  }
+}
+
+template <int SW>
+hipError_t launch_generic_insert_sw(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st) {
+  if (a.len < g.k) return hipSuccess;
+  const uint64_t nk = a.len - g.k + 1;
+  const uint64_t grid = (nk + kGenericTile - 1) / kGenericTile;
+  const RtParams p{(int)g.k, (int)g.s, (int)g.m, (int)g.H, g.nshards - 1};
+  const int aligned = ((uintptr_t)a.seq & 15u) == 0;
+  hipLaunchKernelGGL(insert_generic_kernel<SW>, dim3((unsigned)grid), dim3(kGenericWG), 0, st, a.seq, a.len,
+                     a.starts, aligned, words, p);
+  return hipGetLastError();
+}
+
+template <int SW>
+hipError_t launch_generic_query_sw(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st) {
+  if (a.n_out == 0) return hipSuccess;
+  const uint64_t grid = (a.n_out + kGenericTile - 1) / kGenericTile;
+  const RtParams p{(int)g.k, (int)g.s, (int)g.m, (int)g.H, g.nshards - 1};
+  const int aligned = ((uintptr_t)a.seq & 15u) == 0;
+  hipLaunchKernelGGL(query_generic_kernel<SW>, dim3((unsigned)grid), dim3(kGenericWG), 0, st, a.seq, a.len,
+                     a.starts, aligned, words, p, a.out, a.n_out);
+  return hipGetLastError();
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void mark_starts_kernel(const uint64_t *__restrict__ off, uint64_t nrec, uint64_t len,
+                                   uint32_t *__restrict__ starts) {
+  for (uint64_t r = 1 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrec;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t p = off[r];
+    if (p < len) atomicOr(starts + (p >> 5), 1u << (uint32_t)(p & 31u));
+  }
+}
+
+unsigned grid_for(uint64_t n, unsigned block) {
+  uint64_t g = (n + block - 1) / block;
+  if (g > 65536u) g = 65536u;
+  if (g == 0) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_insert_generic(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st) {
+  switch (g.shard_words) {
+    case 4: return launch_generic_insert_sw<4>(g, words, a, st);
+    case 8: return launch_generic_insert_sw<8>(g, words, a, st);
+    case 16: return launch_generic_insert_sw<16>(g, words, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st) {
+  switch (g.shard_words) {
+    case 4: return launch_generic_query_sw<4>(g, words, a, st);
+    case 8: return launch_generic_query_sw<8>(g, words, a, st);
+    case 16: return launch_generic_query_sw<16>(g, words, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_record_starts(const uint64_t *off, uint64_t nrec, uint64_t len, uint32_t *starts,
+                                     hipStream_t st) {
+  if (nrec < 2) return hipSuccess;
+  hipLaunchKernelGGL(mark_starts_kernel, dim3(grid_for(nrec - 1, 256)), dim3(256), 0, st, off, nrec, len, starts);
+  return hipGetLastError();
+}
+
+}  // namespace sbf

@@ -1,0 +1,383 @@
+// Super-k-mer ("rolling") insert and query kernels for gfx950.
+//
+// Instead of one k-mer per lane (the paper's Algorithms 1 and 2 repeat k-m+1
+// m-mer hashes and k-s+1 s-mer hashes per k-mer), each lane walks a run of L
+// consecutive k-mers and hashes every m-mer and s-mer position once:
+//   * the minimum over the w = k-m+1 m-mer hashes of each k-mer comes from a
+//     van Herk / Gil-Werman sliding minimum (suffix minima of one block of w
+//     hashes against prefix minima of the next: 3 compares per position);
+//   * consecutive valid k-mers with the same shard form a segment (the
+//     super-k-mer of Section "Minimizers and Super-k-mers", split where the
+//     shard changes); the lane ORs the one-hot masks of the segment's s-mers
+//     in registers and issues one 64-bit atomic OR per word when the segment
+//     ends - the per-lane form of the paper's segmented reduction with the
+//     run head doing the atomics (Algorithm 1);
+//   * the query computes every k-mer's shard and the bit addresses of every
+//     s-mer in the same way, stages them in LDS, and then tests k-mers with
+//     one lane per k-mer: the first lane of each run of equal shards in the
+//     wave loads the 32-byte shard and the other lanes of the run read it with
+//     ds_bpermute (the paper's leader load and broadcast, Algorithm 2).
+// Every result is bit-identical to the per-k-mer definition: OR is
+// commutative and idempotent, and a k-mer is tested in its own shard.
+#include "sbf_device.h"
+#include "sbf_internal.h"
+
+#include <type_traits>
+
+namespace sbf {
+namespace {
+
+// Granules (16 bases) a lane reads: L + K - 1 bases plus one for the funnel
+// shift of the last window.
+template <int K, int L>
+constexpr int lane_granules() { return (L + K - 1 + 15) / 16 + 1; }
+
+template <int M>
+__device__ __forceinline__ uint32_t mmer_at(const uint32_t *a, int j) {
+  static_assert(M >= 1 && M <= 16, "m-mers of the rolling kernels fit 32 bits");
+  return win32(a, j) >> (32 - 2 * M);
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t smer_at(const uint32_t *a, int j) {
+  if constexpr (S <= 16) {
+    return (uint64_t)(win32(a, j) >> (32 - 2 * S));
+  } else {
+    const uint32_t hi = win32(a, j) >> (64 - 2 * S);
+    const uint32_t lo = win32(a, j + S - 16);
+    return ((uint64_t)hi << 32) | lo;
+  }
+}
+
+template <int H>
+__device__ __forceinline__ void smer_onehots(uint64_t g, uint64_t (&oh)[4]) {
+  oh[0] = oh[1] = oh[2] = oh[3] = 0;
+#pragma unroll
+  for (int t = 0; t < H; ++t) oh[t & 3] |= 1ull << bit_address<H>(g, t);
+}
+
+template <int NW>
+__device__ __forceinline__ void flush_segment(uint64_t *__restrict__ words, uint32_t shard, const uint64_t (&m)[4]) {
+  uint64_t *p = words + 4ull * (uint64_t)shard;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) atomic_or64(p + w, m[w]);
+}
+
+// ---------------------------------------------------------------------------
+// Insert: WG lanes x L k-mers per workgroup tile.
+// ---------------------------------------------------------------------------
+template <int K, int S, int M, int H, int L, int WG>
+__global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+                                                            const uint32_t *__restrict__ starts, int aligned16,
+                                                            uint64_t *__restrict__ words, uint32_t shard_mask) {
+  constexpr int W = K - M + 1;
+  constexpr int Z = K - S;
+  constexpr int GPL = L / 16;
+  constexpr int NGW = lane_granules<K, L>();
+  constexpr int NGRAN = (WG - 1) * GPL + NGW;
+  constexpr int NW = H < 4 ? H : 4;
+  static_assert(L % 16 == 0 && L + K - 1 <= 64, "a lane's bases fit one 64-bit validity word");
+  static_assert(Z >= 0 && W >= 1, "s <= k and m <= k");
+
+  __shared__ uint32_t s_codes[NGRAN];
+  __shared__ uint32_t s_vb[NGRAN];
+
+  const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(WG * L);
+  stage_granules<WG>(seq, len, base, starts, aligned16 != 0, NGRAN, s_codes, s_vb);
+  __syncthreads();
+
+  const int g0 = threadIdx.x * GPL;
+  uint32_t a[NGW];
+  uint64_t vbits = 0, sbits = 0;
+#pragma unroll
+  for (int i = 0; i < NGW; ++i) {
+    a[i] = s_codes[g0 + i];
+    if (i < 4) {
+      const uint32_t vb = s_vb[g0 + i];
+      vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
+      sbits |= (uint64_t)(vb >> 16) << (16 * i);
+    }
+  }
+  const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
+  if (kv == 0) return;
+
+  // one-hot masks of s-mers r .. r+Z, OR-ed: A(r).  For Z = 3 the window OR
+  // reuses pairs P(j) = oh(j) | oh(j+1): A(r) = P(r) | P(r+2).
+  uint64_t oh[L + Z][4];
+  uint64_t pr[L + Z][4];
+#pragma unroll
+  for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
+  if constexpr (Z == 3) {
+#pragma unroll
+    for (int j = 0; j + 1 < Z; ++j)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
+  }
+
+  uint64_t seg[4] = {0, 0, 0, 0};
+  uint32_t cur = 0;
+  bool open = false;
+
+  // van Herk sliding minimum: suf[i] = min(h[qW+i .. qW+W-1]) of block q
+  uint64_t suf[W];
+  {
+    uint64_t hb[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
+    suf[W - 1] = hb[W - 1];
+#pragma unroll
+    for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+  }
+
+#pragma unroll
+  for (int q = 0; q * W < L; ++q) {
+    uint64_t hb[W];
+    uint64_t pre = ~0ull;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      const int r = q * W + i;
+      if (r < L) {
+        uint64_t mu;
+        if (i == 0) {
+          mu = suf[0];
+        } else {
+          hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+          pre = umin64(pre, hb[i - 1]);
+          mu = umin64(suf[i], pre);
+        }
+        // newest s-mer of k-mer r
+        smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
+        uint64_t A[4];
+        if constexpr (Z == 3) {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
+            A[w] = pr[r][w] | pr[r + 2][w];
+          }
+        } else {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            uint64_t x = oh[r][w];
+#pragma unroll
+            for (int j = 1; j <= Z; ++j) x |= oh[r + j][w];
+            A[w] = x;
+          }
+        }
+        const bool v = (kv >> r) & 1ull;
+        const uint32_t sh = (uint32_t)mu & shard_mask;
+        const bool cont = open && v && sh == cur;
+        if (open && !cont) flush_segment<NW>(words, cur, seg);
+        const uint64_t keep = cont ? ~0ull : 0ull;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) seg[w] = (seg[w] & keep) | A[w];
+        open = v;
+        cur = sh;
+      }
+    }
+    if ((q + 1) * W < L) {
+      hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+      suf[W - 1] = hb[W - 1];
+#pragma unroll
+      for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+    }
+  }
+  if (open) flush_segment<NW>(words, cur, seg);
+}
+
+// ---------------------------------------------------------------------------
+// Query: phase 1 (16 k-mers per lane) writes shards and s-mer bit addresses to
+// LDS; phase 2 tests one k-mer per lane.
+// ---------------------------------------------------------------------------
+template <int H>
+using bit_pack_t = typename std::conditional<(H <= 4), uint32_t, uint64_t>::type;
+
+template <int H>
+__device__ __forceinline__ bit_pack_t<H> pack_bit_addresses(uint64_t g) {
+  bit_pack_t<H> p = 0;
+#pragma unroll
+  for (int t = 0; t < H; ++t) p |= (bit_pack_t<H>)bit_address<H>(g, t) << (8 * t);
+  return p;
+}
+
+template <int K, int S, int M, int H, int WG, bool SHARE>
+__global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+                                                           const uint32_t *__restrict__ starts, int aligned16,
+                                                           const uint64_t *__restrict__ words, uint32_t shard_mask,
+                                                           uint8_t *__restrict__ out, uint64_t n_out) {
+  constexpr int L = 16;
+  constexpr int TILE = WG * L;
+  constexpr int W = K - M + 1;
+  constexpr int Z = K - S;
+  constexpr int NGW = lane_granules<K, L>();
+  constexpr int NGRAN = (WG - 1) + NGW;
+  static_assert(H <= 8, "bit addresses pack into 8 bytes");
+  using Pack = bit_pack_t<H>;
+
+  __shared__ uint32_t s_codes[NGRAN];
+  __shared__ uint32_t s_vb[NGRAN];
+  __shared__ uint32_t s_shard[TILE];
+  __shared__ Pack s_bits[TILE + Z];
+  __shared__ uint32_t s_kv[WG];
+
+  const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)TILE;
+  stage_granules<WG>(seq, len, base, starts, aligned16 != 0, NGRAN, s_codes, s_vb);
+  __syncthreads();
+
+  // ---- phase 1: lane t owns k-mers 16t .. 16t+15 of the tile ----
+  {
+    const int t = threadIdx.x;
+    uint32_t a[NGW];
+    uint64_t vbits = 0, sbits = 0;
+#pragma unroll
+    for (int i = 0; i < NGW; ++i) {
+      a[i] = s_codes[t + i];
+      if (i < 4) {
+        const uint32_t vb = s_vb[t + i];
+        vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
+        sbits |= (uint64_t)(vb >> 16) << (16 * i);
+      }
+    }
+    s_kv[t] = (uint32_t)(kmer_valid_mask<K>(vbits, sbits) & 0xFFFFull);
+
+    uint64_t suf[W];
+    {
+      uint64_t hb[W];
+#pragma unroll
+      for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
+      suf[W - 1] = hb[W - 1];
+#pragma unroll
+      for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+    }
+#pragma unroll
+    for (int q = 0; q * W < L; ++q) {
+      uint64_t hb[W];
+      uint64_t pre = ~0ull;
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        const int r = q * W + i;
+        if (r < L) {
+          uint64_t mu;
+          if (i == 0) {
+            mu = suf[0];
+          } else {
+            hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+            pre = umin64(pre, hb[i - 1]);
+            mu = umin64(suf[i], pre);
+          }
+          s_shard[t * L + r] = (uint32_t)mu & shard_mask;
+        }
+      }
+      if ((q + 1) * W < L) {
+        hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+        suf[W - 1] = hb[W - 1];
+#pragma unroll
+        for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j) s_bits[t * L + j] = pack_bit_addresses<H>(smer_hash(smer_at<S>(a, j)));
+    if (t == WG - 1) {
+#pragma unroll
+      for (int j = L; j < L + Z; ++j) s_bits[t * L + j] = pack_bit_addresses<H>(smer_hash(smer_at<S>(a, j)));
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: one k-mer per lane, consecutive k-mers across the wave ----
+  const int lane = threadIdx.x & 63;
+#pragma unroll 2
+  for (int i = 0; i < L; ++i) {
+    const int q = i * WG + threadIdx.x;
+    const bool v = (s_kv[q >> 4] >> (q & 15)) & 1u;
+    const uint32_t shard = s_shard[q];
+    uint32_t wd[8];
+    if constexpr (SHARE) {
+      const int qp = q > 0 ? q - 1 : 0;
+      const bool pv = q > 0 && ((s_kv[qp >> 4] >> (qp & 15)) & 1u);
+      const bool head = v && (lane == 0 || !pv || s_shard[qp] != shard);
+      const uint64_t heads = __ballot(head);
+      const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+      const int leader = upto ? 63 - __clzll((long long)upto) : lane;
+      if (head) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)shard);
+        const uint4 lo = p[0], hi = p[1];
+        wd[0] = lo.x; wd[1] = lo.y; wd[2] = lo.z; wd[3] = lo.w;
+        wd[4] = hi.x; wd[5] = hi.y; wd[6] = hi.z; wd[7] = hi.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wd[j] = 0;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) wd[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(leader << 2, (int)wd[j]);
+    } else {
+      if (v) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)shard);
+        const uint4 lo = p[0], hi = p[1];
+        wd[0] = lo.x; wd[1] = lo.y; wd[2] = lo.z; wd[3] = lo.w;
+        wd[4] = hi.x; wd[5] = hi.y; wd[6] = hi.z; wd[7] = hi.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wd[j] = 0;
+      }
+    }
+    uint64_t w4[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) w4[w] = ((uint64_t)wd[2 * w + 1] << 32) | wd[2 * w];
+    uint32_t acc = 0xFFFFFFFFu;
+#pragma unroll
+    for (int p = 0; p <= Z; ++p) {
+      const Pack b = s_bits[q + p];
+#pragma unroll
+      for (int t = 0; t < H; ++t) acc &= (uint32_t)(w4[t & 3] >> ((uint32_t)(b >> (8 * t)) & 63u));
+    }
+    const uint64_t pos = base + (uint64_t)q;
+    if (pos < n_out) out[pos] = v ? (uint8_t)(acc & 1u) : (uint8_t)0;
+  }
+}
+
+constexpr int kInsertL = 32;
+constexpr int kInsertWG = 256;
+constexpr int kQueryWG = 256;
+
+template <int K, int S, int M, int H>
+hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, hipStream_t st) {
+  if (a.len < (uint64_t)K) return hipSuccess;
+  const uint64_t nk = a.len - K + 1;
+  const uint64_t tile = (uint64_t)kInsertL * kInsertWG;
+  const uint64_t grid = (nk + tile - 1) / tile;
+  const int aligned = ((uintptr_t)a.seq & 15u) == 0;
+  hipLaunchKernelGGL((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG>), dim3((unsigned)grid),
+                     dim3(kInsertWG), 0, st, a.seq, a.len, a.starts, aligned, words, shard_mask);
+  return hipGetLastError();
+}
+
+template <int K, int S, int M, int H>
+hipError_t query_rolling(const uint64_t *words, uint32_t shard_mask, const SeqArgs &a, hipStream_t st) {
+  if (a.n_out == 0) return hipSuccess;
+  const uint64_t tile = 16ull * kQueryWG;
+  const uint64_t grid = (a.n_out + tile - 1) / tile;
+  const int aligned = ((uintptr_t)a.seq & 15u) == 0;
+  hipLaunchKernelGGL((query_rolling_kernel<K, S, M, H, kQueryWG, true>), dim3((unsigned)grid), dim3(kQueryWG), 0,
+                     st, a.seq, a.len, a.starts, aligned, words, shard_mask, a.out, a.n_out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool rolling_supported(const Geometry &g) {
+  return g.shard_words == 4 && g.nshards <= (1ull << 32) && g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4;
+}
+
+hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st) {
+  const uint32_t mask = (uint32_t)(g.nshards - 1);
+  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4) return insert_rolling<31, 28, 16, 4>(words, mask, a, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st) {
+  const uint32_t mask = (uint32_t)(g.nshards - 1);
+  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4) return query_rolling<31, 28, 16, 4>(words, mask, a, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sbf

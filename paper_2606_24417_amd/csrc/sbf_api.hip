@@ -1,0 +1,466 @@
+// Host runtime behind the C ABI of include/sbf.h: filter objects, parameter
+// validation, staging of host input, record-start scratch per stream, and
+// dispatch to the rolling or generic kernels.
+#include "sbf.h"
+#include "sbf_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+
+using sbf::Geometry;
+using sbf::SeqArgs;
+
+namespace {
+
+thread_local int g_err = SBF_OK;
+thread_local std::string g_msg;
+
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int set_error(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = code;
+  g_msg = buf;
+  return code;
+}
+
+int ok() {
+  g_err = SBF_OK;
+  g_msg.clear();
+  return SBF_OK;
+}
+
+int hip_error(hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory) return set_error(SBF_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return set_error(SBF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SBF_HIP(call, what)                  \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_error(e_, what); \
+  } while (0)
+
+constexpr uint64_t kMaxBits = 1ull << 40;
+constexpr uint64_t kDefaultStaging = 256ull << 20;
+
+struct Scratch {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sbf_filter {
+  Geometry g{};
+  uint64_t *words = nullptr;  // device, 4 * nshards
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int variant = SBF_VARIANT_AUTO;
+  uint64_t staging = kDefaultStaging;
+  // host entry points: device staging
+  Scratch stage_seq, stage_out, stage_off;
+  // record-start bits, one buffer per stream
+  std::mutex mu;
+  std::unordered_map<hipStream_t, Scratch> starts;
+};
+
+namespace {
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t n = 1;
+  while (n < x) n <<= 1;
+  return n;
+}
+
+bool use_rolling(const sbf_filter *f) {
+  if (f->variant == SBF_VARIANT_GENERIC) return false;
+  return sbf::rolling_supported(f->g);
+}
+
+hipStream_t pick(const sbf_filter *f, void *stream) { return stream ? (hipStream_t)stream : f->stream; }
+
+int grow(Scratch &s, size_t bytes, const char *what) {
+  if (s.bytes >= bytes) return SBF_OK;
+  if (s.ptr) {
+    hipError_t e = hipFree(s.ptr);
+    s.ptr = nullptr;
+    s.bytes = 0;
+    if (e != hipSuccess) return hip_error(e, what);
+  }
+  size_t want = std::max<size_t>(bytes, 4096);
+  hipError_t e = hipMalloc(&s.ptr, want);
+  if (e != hipSuccess) {
+    s.ptr = nullptr;
+    return hip_error(e, what);
+  }
+  s.bytes = want;
+  return SBF_OK;
+}
+
+int run_insert(sbf_filter *f, const SeqArgs &a, hipStream_t st) {
+  hipError_t e = use_rolling(f) ? sbf::launch_insert_rolling(f->g, f->words, a, st)
+                                : sbf::launch_insert_generic(f->g, f->words, a, st);
+  if (e != hipSuccess) return hip_error(e, "insert kernel launch");
+  return SBF_OK;
+}
+
+int run_query(sbf_filter *f, const SeqArgs &a, hipStream_t st) {
+  hipError_t e = use_rolling(f) ? sbf::launch_query_rolling(f->g, f->words, a, st)
+                                : sbf::launch_query_generic(f->g, f->words, a, st);
+  if (e != hipSuccess) return hip_error(e, "query kernel launch");
+  return SBF_OK;
+}
+
+// record-start bits for a batch on stream st; returns null when not needed
+int record_starts(sbf_filter *f, const uint64_t *d_off, uint64_t nrec, uint64_t len, hipStream_t st,
+                  const uint32_t **out) {
+  *out = nullptr;
+  if (nrec < 2 || len == 0) return SBF_OK;
+  const uint64_t nw = (len + 31) / 32;
+  Scratch *s;
+  {
+    std::lock_guard<std::mutex> lk(f->mu);
+    s = &f->starts[st];
+  }
+  if (s->bytes < nw * 4) {
+    // the old buffer may still be in use by earlier work on this stream
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_error(e, "record-start scratch");
+    int rc = grow(*s, nw * 4, "record-start scratch");
+    if (rc) return rc;
+  }
+  uint32_t *w = (uint32_t *)s->ptr;
+  hipError_t e = sbf::launch_fill_u32(w, nw, 0u, st);
+  if (e == hipSuccess) e = sbf::launch_mark_record_starts(d_off, nrec, len, w, st);
+  if (e != hipSuccess) return hip_error(e, "record-start marking");
+  *out = w;
+  return SBF_OK;
+}
+
+int check_filter(const sbf_filter *f) {
+  if (!f) return set_error(SBF_E_INVAL, "filter is NULL");
+  return SBF_OK;
+}
+
+int set_device(const sbf_filter *f) {
+  SBF_HIP(hipSetDevice(f->device), "hipSetDevice");
+  return SBF_OK;
+}
+
+// Host-sequence insert or query of one record batch, staged in chunks.
+// Chunk boundaries fall on k-mer starts; a chunk carries k-1 extra bases.
+int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out, bool query) {
+  const uint64_t k = f->g.k;
+  const uint64_t total = off[nrec];
+  const uint64_t budget = std::max<uint64_t>(f->staging, 4096);
+  const uint64_t span = budget > k ? budget - (k - 1) : 1;  // k-mer starts per chunk
+  hipStream_t st = f->stream;
+  int rc;
+  if ((rc = grow(f->stage_seq, budget + 64, "staging buffer"))) return rc;
+  if (query && (rc = grow(f->stage_out, budget + 64, "staging buffer"))) return rc;
+  uint64_t r0 = 0;  // first record overlapping the chunk
+  for (uint64_t c0 = 0; c0 < total; c0 += span) {
+    const uint64_t c1 = std::min(total, c0 + span);       // k-mer starts [c0, c1)
+    const uint64_t e1 = std::min(total, c1 + k - 1);      // bases [c0, e1)
+    while (r0 + 1 < nrec && off[r0 + 1] <= c0) ++r0;
+    // record starts inside (c0, e1) relative to c0
+    uint64_t r1 = r0;
+    while (r1 + 1 < nrec && off[r1 + 1] < e1) ++r1;
+    const uint64_t nloc = r1 - r0 + 1;  // records overlapping the chunk
+    const uint64_t len = e1 - c0;
+    SBF_HIP(hipMemcpyAsync(f->stage_seq.ptr, seq + c0, len, hipMemcpyHostToDevice, st), "copy sequence to device");
+    const uint32_t *starts = nullptr;
+    if (nloc > 1) {
+      // local offsets: 0, then each record start inside the chunk, then len
+      if ((rc = grow(f->stage_off, (nloc + 1) * 8, "staging buffer"))) return rc;
+      uint64_t *loc = new (std::nothrow) uint64_t[nloc + 1];
+      if (!loc) return set_error(SBF_E_NOMEM, "host offsets");
+      loc[0] = 0;
+      for (uint64_t r = 1; r < nloc; ++r) loc[r] = off[r0 + r] - c0;
+      loc[nloc] = len;
+      hipError_t e = hipMemcpyAsync(f->stage_off.ptr, loc, (nloc + 1) * 8, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      delete[] loc;
+      if (e != hipSuccess) return hip_error(e, "copy offsets to device");
+      if ((rc = record_starts(f, (const uint64_t *)f->stage_off.ptr, nloc, len, st, &starts))) return rc;
+    }
+    SeqArgs a{(const uint8_t *)f->stage_seq.ptr, len, starts, nullptr, 0};
+    if (query) {
+      a.out = (uint8_t *)f->stage_out.ptr;
+      a.n_out = c1 - c0;
+      if ((rc = run_query(f, a, st))) return rc;
+      SBF_HIP(hipMemcpyAsync(out + c0, f->stage_out.ptr, c1 - c0, hipMemcpyDeviceToHost, st), "copy answers to host");
+    } else {
+      if ((rc = run_insert(f, a, st))) return rc;
+    }
+    SBF_HIP(hipStreamSynchronize(st), "kernel execution");
+  }
+  return SBF_OK;
+}
+
+int validate_offsets(const uint64_t *off, uint64_t nrec) {
+  if (!off) return set_error(SBF_E_INVAL, "offsets are NULL");
+  if (off[0] != 0) return set_error(SBF_E_INVAL, "off[0] must be 0");
+  for (uint64_t r = 0; r < nrec; ++r)
+    if (off[r + 1] < off[r]) return set_error(SBF_E_INVAL, "offsets decrease at record %llu", (unsigned long long)r);
+  return SBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbf_filter *sbf_create(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits) {
+  if (k < 1 || k > 32 || s < 1 || s > k || m < 1 || m > k || H < 1 || H > 16 || bits < 1 || bits > kMaxBits) {
+    set_error(SBF_E_INVAL,
+              "invalid parameters k=%u s=%u m=%u H=%u bits=%llu (need 1<=s,m<=k<=32, 1<=H<=16, 1<=bits<=2^40)", k, s,
+              m, H, (unsigned long long)bits);
+    return nullptr;
+  }
+  sbf_filter *f = new (std::nothrow) sbf_filter;
+  if (!f) {
+    set_error(SBF_E_NOMEM, "host allocation of the filter object");
+    return nullptr;
+  }
+  f->g.k = k;
+  f->g.s = s;
+  f->g.m = m;
+  f->g.H = H;
+  f->g.shard_words = 4;
+  f->g.nshards = next_pow2(std::max<uint64_t>(1, (bits + 255) / 256));
+  hipError_t e = hipGetDevice(&f->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    hip_error(e, "stream creation");
+    delete f;
+    return nullptr;
+  }
+  const uint64_t nwords = f->g.nshards * f->g.shard_words;
+  e = hipMalloc((void **)&f->words, nwords * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    f->words = nullptr;
+    hip_error(e, "filter allocation");
+    (void)hipStreamDestroy(f->stream);
+    delete f;
+    return nullptr;
+  }
+  e = sbf::launch_fill_u64(f->words, nwords, 0ull, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  if (e != hipSuccess) {
+    hip_error(e, "filter initialisation");
+    (void)hipFree(f->words);
+    (void)hipStreamDestroy(f->stream);
+    delete f;
+    return nullptr;
+  }
+  ok();
+  return f;
+}
+
+void sbf_destroy(sbf_filter *f) {
+  if (!f) return;
+  (void)hipSetDevice(f->device);
+  (void)hipDeviceSynchronize();
+  for (auto &kv : f->starts)
+    if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  if (f->stage_seq.ptr) (void)hipFree(f->stage_seq.ptr);
+  if (f->stage_out.ptr) (void)hipFree(f->stage_out.ptr);
+  if (f->stage_off.ptr) (void)hipFree(f->stage_off.ptr);
+  if (f->words) (void)hipFree(f->words);
+  if (f->stream) (void)hipStreamDestroy(f->stream);
+  delete f;
+}
+
+int sbf_last_error(const char **msg) {
+  if (msg) *msg = g_msg.c_str();
+  return g_err;
+}
+
+uint64_t sbf_num_shards(const sbf_filter *f) { return f ? f->g.nshards : 0; }
+uint64_t sbf_num_bits(const sbf_filter *f) { return f ? f->g.nshards * f->g.shard_words * 64ull : 0; }
+uint64_t sbf_num_words(const sbf_filter *f) { return f ? f->g.nshards * f->g.shard_words : 0; }
+const uint64_t *sbf_device_words(const sbf_filter *f) { return f ? f->words : nullptr; }
+
+int sbf_get_bits(const sbf_filter *f, uint64_t *host_dst, uint64_t nwords) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (!host_dst || nwords != sbf_num_words(f)) return set_error(SBF_E_INVAL, "need %llu words", (unsigned long long)sbf_num_words(f));
+  if ((rc = set_device(f))) return rc;
+  SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
+  SBF_HIP(hipMemcpy(host_dst, f->words, nwords * 8, hipMemcpyDeviceToHost), "copy filter to host");
+  return ok();
+}
+
+int sbf_set_bits(sbf_filter *f, const uint64_t *host_src, uint64_t nwords) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (!host_src || nwords != sbf_num_words(f)) return set_error(SBF_E_INVAL, "need %llu words", (unsigned long long)sbf_num_words(f));
+  if ((rc = set_device(f))) return rc;
+  SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
+  SBF_HIP(hipMemcpy(f->words, host_src, nwords * 8, hipMemcpyHostToDevice), "copy filter to device");
+  return ok();
+}
+
+int sbf_clear(sbf_filter *f, void *stream) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if ((rc = set_device(f))) return rc;
+  hipError_t e = sbf::launch_fill_u64(f->words, sbf_num_words(f), 0ull, pick(f, stream));
+  if (e != hipSuccess) return hip_error(e, "clear kernel launch");
+  return ok();
+}
+
+int sbf_insert_seq_dev(sbf_filter *f, const char *d_seq, uint64_t len, void *stream) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len == 0) return ok();
+  if (!d_seq) return set_error(SBF_E_INVAL, "sequence is NULL");
+  if ((rc = set_device(f))) return rc;
+  SeqArgs a{(const uint8_t *)d_seq, len, nullptr, nullptr, 0};
+  if ((rc = run_insert(f, a, pick(f, stream)))) return rc;
+  return ok();
+}
+
+int sbf_query_seq_dev(sbf_filter *f, const char *d_seq, uint64_t len, uint8_t *d_out, void *stream) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len < f->g.k) return ok();
+  if (!d_seq || !d_out) return set_error(SBF_E_INVAL, "sequence or output is NULL");
+  if ((rc = set_device(f))) return rc;
+  SeqArgs a{(const uint8_t *)d_seq, len, nullptr, d_out, len - f->g.k + 1};
+  if ((rc = run_query(f, a, pick(f, stream)))) return rc;
+  return ok();
+}
+
+int sbf_insert_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off, uint64_t nrec,
+                         void *stream) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len == 0 || nrec == 0) return ok();
+  if (!d_seq || !d_off) return set_error(SBF_E_INVAL, "sequence or offsets are NULL");
+  if ((rc = set_device(f))) return rc;
+  hipStream_t st = pick(f, stream);
+  const uint32_t *starts = nullptr;
+  if ((rc = record_starts(f, d_off, nrec, len, st, &starts))) return rc;
+  SeqArgs a{(const uint8_t *)d_seq, len, starts, nullptr, 0};
+  if ((rc = run_insert(f, a, st))) return rc;
+  return ok();
+}
+
+int sbf_query_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off, uint64_t nrec,
+                        uint8_t *d_out, void *stream) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len == 0 || nrec == 0) return ok();
+  if (!d_seq || !d_off || !d_out) return set_error(SBF_E_INVAL, "sequence, offsets or output is NULL");
+  if ((rc = set_device(f))) return rc;
+  hipStream_t st = pick(f, stream);
+  const uint32_t *starts = nullptr;
+  if ((rc = record_starts(f, d_off, nrec, len, st, &starts))) return rc;
+  SeqArgs a{(const uint8_t *)d_seq, len, starts, d_out, len};
+  if ((rc = run_query(f, a, st))) return rc;
+  return ok();
+}
+
+int sbf_insert_seq(sbf_filter *f, const char *seq, uint64_t len) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len < f->g.k) return ok();
+  if (!seq) return set_error(SBF_E_INVAL, "sequence is NULL");
+  if ((rc = set_device(f))) return rc;
+  const uint64_t off[2] = {0, len};
+  if ((rc = host_batch(f, seq, off, 1, nullptr, false))) return rc;
+  return ok();
+}
+
+int sbf_query_seq(sbf_filter *f, const char *seq, uint64_t len, uint8_t *out) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len < f->g.k) return ok();
+  if (!seq || !out) return set_error(SBF_E_INVAL, "sequence or output is NULL");
+  if ((rc = set_device(f))) return rc;
+  // answers for k-mer starts [0, len-k+1): stage with a per-base output and
+  // copy only the valid prefix of each chunk
+  const uint64_t off[2] = {0, len};
+  const uint64_t k = f->g.k;
+  const uint64_t n_out = len - k + 1;
+  const uint64_t budget = std::max<uint64_t>(f->staging, 4096);
+  const uint64_t span = budget > k ? budget - (k - 1) : 1;
+  if ((rc = grow(f->stage_seq, budget + 64, "staging buffer"))) return rc;
+  if ((rc = grow(f->stage_out, budget + 64, "staging buffer"))) return rc;
+  hipStream_t st = f->stream;
+  (void)off;
+  for (uint64_t c0 = 0; c0 < n_out; c0 += span) {
+    const uint64_t c1 = std::min(n_out, c0 + span);
+    const uint64_t e1 = c1 + k - 1;
+    SBF_HIP(hipMemcpyAsync(f->stage_seq.ptr, seq + c0, e1 - c0, hipMemcpyHostToDevice, st), "copy sequence to device");
+    SeqArgs a{(const uint8_t *)f->stage_seq.ptr, e1 - c0, nullptr, (uint8_t *)f->stage_out.ptr, c1 - c0};
+    if ((rc = run_query(f, a, st))) return rc;
+    SBF_HIP(hipMemcpyAsync(out + c0, f->stage_out.ptr, c1 - c0, hipMemcpyDeviceToHost, st), "copy answers to host");
+    SBF_HIP(hipStreamSynchronize(st), "kernel execution");
+  }
+  return ok();
+}
+
+int sbf_insert_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (nrec == 0) return ok();
+  if ((rc = validate_offsets(off, nrec))) return rc;
+  if (off[nrec] == 0) return ok();
+  if (!seq) return set_error(SBF_E_INVAL, "sequence is NULL");
+  if ((rc = set_device(f))) return rc;
+  if ((rc = host_batch(f, seq, off, nrec, nullptr, false))) return rc;
+  return ok();
+}
+
+int sbf_query_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (nrec == 0) return ok();
+  if ((rc = validate_offsets(off, nrec))) return rc;
+  if (off[nrec] == 0) return ok();
+  if (!seq || !out) return set_error(SBF_E_INVAL, "sequence or output is NULL");
+  if ((rc = set_device(f))) return rc;
+  if ((rc = host_batch(f, seq, off, nrec, out, true))) return rc;
+  return ok();
+}
+
+int sbf_set_variant(sbf_filter *f, int variant) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (variant == SBF_VARIANT_ROLLING && !sbf::rolling_supported(f->g))
+    return set_error(SBF_E_INVAL, "no rolling kernel for k=%u s=%u m=%u H=%u", f->g.k, f->g.s, f->g.m, f->g.H);
+  if (variant != SBF_VARIANT_AUTO && variant != SBF_VARIANT_ROLLING && variant != SBF_VARIANT_GENERIC)
+    return set_error(SBF_E_INVAL, "unknown variant %d", variant);
+  f->variant = variant;
+  return ok();
+}
+
+int sbf_get_variant(const sbf_filter *f) {
+  if (!f) return set_error(SBF_E_INVAL, "filter is NULL");
+  ok();
+  return use_rolling(f) ? SBF_VARIANT_ROLLING : SBF_VARIANT_GENERIC;
+}
+
+int sbf_set_staging_bytes(sbf_filter *f, uint64_t bytes) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (bytes < 4096) return set_error(SBF_E_INVAL, "staging must be at least 4096 bytes");
+  f->staging = bytes;
+  return ok();
+}
+
+}  // extern "C"

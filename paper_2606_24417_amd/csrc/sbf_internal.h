@@ -1,0 +1,42 @@
+// Host-side interface between the C ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbf {
+
+struct Geometry {
+  uint32_t k, s, m, H;
+  uint32_t shard_words;  // 64-bit words per shard (4 = the paper's 256-bit shard)
+  uint64_t nshards;      // power of two, at most 2^32
+};
+
+// One launch over a device sequence.  Insert: every valid k-mer starting in
+// [0, len-k+1).  Query: out[i] for i in [0, n_out) (k-mers that leave the
+// sequence or cross a record start are invalid and answer 0).
+struct SeqArgs {
+  const uint8_t *seq;
+  uint64_t len;
+  const uint32_t *starts;  // record-start bits (1 bit per base) or null
+  uint8_t *out;            // query only
+  uint64_t n_out;          // query only
+};
+
+// Rolling kernels exist for a few compiled parameter sets.
+bool rolling_supported(const Geometry &g);
+
+hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st);
+hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);
+hipError_t launch_insert_generic(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st);
+hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);
+
+// Utility kernels.
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st);
+// Set bit off[r] of `starts` for r = 1 .. nrec-1 (starts must be zeroed;
+// ceil(len/32) words).
+hipError_t launch_mark_record_starts(const uint64_t *off, uint64_t nrec, uint64_t len, uint32_t *starts,
+                                     hipStream_t st);
+
+}  // namespace sbf

@@ -1,0 +1,239 @@
+"""ctypes binding of ``libsbf.so`` (declared in include/sbf.h).
+
+Argument marshalling only: every step of insert and query runs in the HIP
+kernels of the library.  PyTorch is used for device buffers and streams; CPU
+inputs go through the library's host entry points, CUDA tensors through its
+stream-ordered device entry points on the current torch stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsbf.so")
+
+SBF_OK = 0
+SBF_E_INVAL = -1
+SBF_E_NOMEM = -2
+SBF_E_DEVICE = -3
+VARIANT_AUTO = 0
+VARIANT_ROLLING = 1
+VARIANT_GENERIC = 2
+
+# every function declared in include/sbf.h, with its ctypes signature
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_int = ctypes.c_int
+SIGNATURES = {
+    "sbf_create": (_vp, [_u32, _u32, _u32, _u32, _u64]),
+    "sbf_destroy": (None, [_vp]),
+    "sbf_insert_seq": (_int, [_vp, _vp, _u64]),
+    "sbf_query_seq": (_int, [_vp, _vp, _u64, _vp]),
+    "sbf_last_error": (_int, [ctypes.POINTER(ctypes.c_char_p)]),
+    "sbf_num_shards": (_u64, [_vp]),
+    "sbf_num_bits": (_u64, [_vp]),
+    "sbf_num_words": (_u64, [_vp]),
+    "sbf_get_bits": (_int, [_vp, _vp, _u64]),
+    "sbf_set_bits": (_int, [_vp, _vp, _u64]),
+    "sbf_clear": (_int, [_vp, _vp]),
+    "sbf_device_words": (_vp, [_vp]),
+    "sbf_insert_seq_dev": (_int, [_vp, _vp, _u64, _vp]),
+    "sbf_query_seq_dev": (_int, [_vp, _vp, _u64, _vp, _vp]),
+    "sbf_insert_batch": (_int, [_vp, _vp, _vp, _u64]),
+    "sbf_query_batch": (_int, [_vp, _vp, _vp, _u64, _vp]),
+    "sbf_insert_batch_dev": (_int, [_vp, _vp, _u64, _vp, _u64, _vp]),
+    "sbf_query_batch_dev": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp]),
+    "sbf_set_variant": (_int, [_vp, _int]),
+    "sbf_get_variant": (_int, [_vp]),
+    "sbf_set_staging_bytes": (_int, [_vp, _u64]),
+}
+
+_lib = None
+
+
+class SBFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("sbf error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsbf.so; fails loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsbf.so is not built (run paper_2606_24417_amd/build.py or "
+                              "__graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    msg = ctypes.c_char_p()
+    code = lib().sbf_last_error(ctypes.byref(msg))
+    return code, (msg.value or b"").decode()
+
+
+def _check(rc):
+    if rc != SBF_OK:
+        code, msg = last_error()
+        raise SBFError(rc, msg)
+
+
+def _is_cuda(x) -> bool:
+    return hasattr(x, "is_cuda") and x.is_cuda
+
+
+def _host_u8(seq) -> np.ndarray:
+    if isinstance(seq, (bytes, bytearray)):
+        return np.frombuffer(bytes(seq), dtype=np.uint8)
+    if isinstance(seq, str):
+        return np.frombuffer(seq.encode("ascii"), dtype=np.uint8)
+    if hasattr(seq, "numpy"):
+        seq = seq.numpy()
+    return np.ascontiguousarray(seq, dtype=np.uint8)
+
+
+def _stream_handle(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Filter:
+    """A Super Bloom filter on the current GPU (owns its device bit array)."""
+
+    def __init__(self, k=31, s=28, m=16, H=4, bits=1 << 24):
+        self.k, self.s, self.m, self.H = int(k), int(s), int(m), int(H)
+        h = lib().sbf_create(self.k, self.s, self.m, self.H, int(bits))
+        if not h:
+            code, msg = last_error()
+            raise SBFError(code, msg)
+        self._h = ctypes.c_void_p(h)
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sbf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- geometry and state ------------------------------------------------------
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def num_shards(self) -> int:
+        return lib().sbf_num_shards(self._h)
+
+    @property
+    def num_bits(self) -> int:
+        return lib().sbf_num_bits(self._h)
+
+    @property
+    def num_words(self) -> int:
+        return lib().sbf_num_words(self._h)
+
+    @property
+    def device_words_ptr(self) -> int:
+        return lib().sbf_device_words(self._h)
+
+    @property
+    def variant(self) -> int:
+        return lib().sbf_get_variant(self._h)
+
+    @variant.setter
+    def variant(self, v: int):
+        _check(lib().sbf_set_variant(self._h, int(v)))
+
+    def set_staging_bytes(self, n: int):
+        _check(lib().sbf_set_staging_bytes(self._h, int(n)))
+
+    def get_bits(self) -> np.ndarray:
+        out = np.empty(self.num_words, dtype=np.uint64)
+        _check(lib().sbf_get_bits(self._h, out.ctypes.data_as(ctypes.c_void_p), out.size))
+        return out
+
+    def set_bits(self, words):
+        a = np.ascontiguousarray(words, dtype=np.uint64)
+        _check(lib().sbf_set_bits(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+
+    def clear(self, stream=None):
+        _check(lib().sbf_clear(self._h, _stream_handle(stream) if stream is not None else None))
+
+    # -- insert / query ------------------------------------------------------------
+    def insert(self, seq, offsets=None, stream=None):
+        """Insert a sequence (or a record batch with ``offsets``).  CUDA tensors
+        run stream-ordered on ``stream`` (default: torch's current stream)."""
+        L = lib()
+        if _is_cuda(seq):
+            st = _stream_handle(stream)
+            if offsets is None:
+                _check(L.sbf_insert_seq_dev(self._h, ctypes.c_void_p(seq.data_ptr()), seq.numel(), st))
+            else:
+                _check(L.sbf_insert_batch_dev(self._h, ctypes.c_void_p(seq.data_ptr()), seq.numel(),
+                                              ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1, st))
+            return
+        a = _host_u8(seq)
+        if offsets is None:
+            _check(L.sbf_insert_seq(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+        else:
+            off = np.ascontiguousarray(offsets, dtype=np.uint64)
+            _check(L.sbf_insert_batch(self._h, a.ctypes.data_as(ctypes.c_void_p),
+                                      off.ctypes.data_as(ctypes.c_void_p), off.size - 1))
+
+    def query(self, seq, offsets=None, out=None, stream=None):
+        """Answers as uint8 0/1.  A single sequence gives len-k+1 answers; a
+        record batch gives one answer per base position (len of the batch)."""
+        L = lib()
+        if _is_cuda(seq):
+            import torch
+
+            st = _stream_handle(stream)
+            n = seq.numel() if offsets is not None else max(0, seq.numel() - self.k + 1)
+            if out is None:
+                out = torch.empty(n, dtype=torch.uint8, device=seq.device)
+            if offsets is None:
+                _check(L.sbf_query_seq_dev(self._h, ctypes.c_void_p(seq.data_ptr()), seq.numel(),
+                                           ctypes.c_void_p(out.data_ptr()), st))
+            else:
+                _check(L.sbf_query_batch_dev(self._h, ctypes.c_void_p(seq.data_ptr()), seq.numel(),
+                                             ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
+                                             ctypes.c_void_p(out.data_ptr()), st))
+            return out
+        a = _host_u8(seq)
+        if offsets is None:
+            n = max(0, a.size - self.k + 1)
+            res = np.zeros(n, dtype=np.uint8) if out is None else out
+            if n:
+                _check(L.sbf_query_seq(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size,
+                                       res.ctypes.data_as(ctypes.c_void_p)))
+            return res
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        res = np.zeros(a.size, dtype=np.uint8) if out is None else out
+        _check(L.sbf_query_batch(self._h, a.ctypes.data_as(ctypes.c_void_p), off.ctypes.data_as(ctypes.c_void_p),
+                                 off.size - 1, res.ctypes.data_as(ctypes.c_void_p)))
+        return res

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Every test builds the same seeded inputs for both sides, runs the library
+through its C ABI (ctypes binding), and compares the whole filter bit array
+and every query answer with the oracle.  Sizes span several workgroup tiles
+(8192 k-mers per insert tile, 4096 per query tile, 1024 per generic tile)
+with ragged tails.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_24417_amd
+
+    paper_2606_24417_amd.lib()
+    print("GPU:", torch.cuda.get_device_name(0), flush=True)
+
+
+def Filter(*a, **kw):
+    from paper_2606_24417_amd import Filter as F
+
+    return F(*a, **kw)
+
+
+VARIANTS = {"rolling": 1, "generic": 2}
+
+
+def dev(x):
+    return torch.from_numpy(np.array(x, copy=True)).cuda()
+
+
+def gpu_run(params, inserts, query, variant="auto", path="dev", staging=None):
+    """inserts: list of (seq, off|None); query: (seq, off|None).  Returns the
+    filter words and the answers."""
+    k, s, m, H, bits = params
+    f = Filter(k, s, m, H, bits)
+    if variant != "auto":
+        f.variant = VARIANTS[variant]
+    if staging:
+        f.set_staging_bytes(staging)
+    for seq, off in inserts:
+        if path == "dev":
+            f.insert(dev(seq), None if off is None else dev(off.astype(np.uint64).view(np.int64)))
+        else:
+            f.insert(seq, off)
+    ans = None
+    if query is not None:
+        qs, qo = query
+        if path == "dev":
+            ans = f.query(dev(qs), None if qo is None else dev(qo.astype(np.uint64).view(np.int64)))
+            torch.cuda.synchronize()
+            ans = ans.cpu().numpy()
+        else:
+            ans = f.query(qs, qo)
+    torch.cuda.synchronize()
+    bits = f.get_bits()
+    f.close()
+    return bits, ans
+
+
+def oracle_run(params, inserts, query):
+    k, s, m, H, bits = params
+    p = oracle.Params(k, s, m, H, bits)
+    F = p.empty()
+    for seq, off in inserts:
+        oracle.insert(p, F, seq, off)
+    ans = None
+    if query is not None:
+        ans = oracle.query(p, F, query[0], query[1])
+    return F, ans
+
+
+def assert_same(got, want, what):
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError("%s differ at %d of %d positions, first %s: got %s want %s" % (
+            what, bad.size, got.size, bad[:5].tolist(), got[bad[:5]].tolist(), want[bad[:5]].tolist()))
+
+
+def check(params, inserts, query, **kw):
+    gb, ga = gpu_run(params, inserts, query, **kw)
+    ob, oa = oracle_run(params, inserts, query)
+    assert_same(gb, ob, "filter words")
+    if query is not None:
+        assert ga.shape == oa.shape
+        assert_same(ga, oa, "answers")
+    return ob, oa
+
+
+def noisy(rng, n, p_invalid=0.0, lower=0.0):
+    seq = synth.uniform_acgt(n, int(rng.integers(1 << 30))).copy()
+    if p_invalid:
+        bad = rng.random(n) < p_invalid
+        seq[bad] = rng.choice(np.frombuffer(b"NnX-\x00\xff.RY", dtype=np.uint8), bad.sum())
+    if lower:
+        lw = rng.random(n) < lower
+        seq[lw] |= 0x20
+    return seq
+
+
+HOT = (31, 28, 16, 4)
+
+
+@pytest.mark.parametrize("variant", ["rolling", "generic"])
+@pytest.mark.parametrize("path", ["dev", "host"])
+def test_tiny_workload(variant, path):
+    """1 Mbp into 2^24 bits; query a 500 kbp substring plus 500 kbp fresh."""
+    w = synth.tiny_workload()
+    print("case tiny", variant, path, flush=True)
+    params = (w["k"], w["s"], w["m"], w["H"], w["bits"])
+    _, ans = check(params, [w["insert"]], w["query"], variant=variant, path=path)
+    n_pos = 500_000 - 30
+    assert ans[:n_pos].sum() == n_pos  # no false negatives
+
+
+@pytest.mark.parametrize("n", [0, 1, 30, 31, 32, 33, 64, 4126, 4127, 4128, 8222, 8223, 8224, 12345, 50_000])
+def test_lengths_around_tiles(n):
+    rng = np.random.default_rng(n)
+    seq = noisy(rng, n, 0.002, 0.1)
+    print("case length", n, flush=True)
+    for variant in ("rolling", "generic"):
+        check(HOT + (1 << 14,), [(seq, None)], (seq, None), variant=variant)
+
+
+@pytest.mark.parametrize("bits", [1, 256, 257, 4096, 1 << 20, 1 << 30])
+@pytest.mark.parametrize("p_invalid", [0.0, 0.01, 0.2])
+def test_filter_sizes_and_invalid_bases(bits, p_invalid):
+    rng = np.random.default_rng(bits % 1000 + int(p_invalid * 100))
+    ins = noisy(rng, 30_000, p_invalid, 0.05)
+    q = np.concatenate([ins[5000:15000], noisy(rng, 20_000, p_invalid)])
+    print("case bits", bits, p_invalid, flush=True)
+    check(HOT + (bits,), [(ins, None)], (q, None))
+
+
+@pytest.mark.parametrize("k,s,m,H", [(31, 28, 16, 1), (31, 28, 16, 8), (31, 24, 12, 4), (31, 31, 16, 4),
+                                     (32, 32, 32, 1), (32, 20, 10, 3), (21, 19, 11, 16), (21, 17, 9, 11),
+                                     (9, 6, 5, 2), (1, 1, 1, 1), (16, 16, 8, 5), (31, 28, 20, 4)])
+def test_generic_parameters(k, s, m, H):
+    rng = np.random.default_rng(k * 100 + s * 10 + H)
+    ins = noisy(rng, 20_000, 0.003)
+    q = np.concatenate([ins[:7000], noisy(rng, 7000, 0.003)])
+    print("case params", k, s, m, H, flush=True)
+    check((k, s, m, H, 1 << 16), [(ins, None)], (q, None))
+
+
+def random_batch(rng, nrec, maxlen, p_invalid=0.0):
+    lens = rng.integers(0, maxlen + 1, nrec)
+    lens[rng.random(nrec) < 0.1] = 0
+    off = np.zeros(nrec + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(lens)
+    return noisy(rng, int(off[-1]), p_invalid), off
+
+
+@pytest.mark.parametrize("variant", ["rolling", "generic"])
+@pytest.mark.parametrize("path", ["dev", "host"])
+def test_record_batches(variant, path):
+    rng = np.random.default_rng(5)
+    ins = random_batch(rng, 700, 400, 0.002)
+    q = random_batch(rng, 600, 300)
+    # some query records are copies of inserted records
+    qs = np.concatenate([ins[0][: int(ins[1][50])], q[0]])
+    qo = np.concatenate([ins[1][:51], q[1][1:] + ins[1][50]])
+    print("case batch", variant, path, flush=True)
+    check(HOT + (1 << 16,), [ins], (qs, qo), variant=variant, path=path)
+
+
+def test_host_chunking_with_small_staging():
+    rng = np.random.default_rng(6)
+    ins = random_batch(rng, 300, 2000, 0.001)
+    single = noisy(rng, 50_000, 0.001)
+    q = random_batch(rng, 200, 1000)
+    print("case chunking", flush=True)
+    check(HOT + (1 << 16,), [ins, (single, None)], q, path="host", staging=4096)
+    check(HOT + (1 << 16,), [(single, None)], (single, None), path="host", staging=5000)
+
+
+def test_unaligned_device_pointers():
+    rng = np.random.default_rng(7)
+    base = noisy(rng, 40_000, 0.001)
+    p = oracle.Params(*HOT, 1 << 16)
+    for shift in (1, 3, 8, 15):
+        t = dev(base)
+        f = Filter(*HOT, 1 << 16)
+        f.insert(t[shift:])
+        ans = f.query(t[shift + 5:])
+        torch.cuda.synchronize()
+        F = oracle.insert(p, p.empty(), base[shift:])
+        assert_same(f.get_bits(), F, "filter words (shift %d)" % shift)
+        assert_same(ans.cpu().numpy(), oracle.query(p, F, base[shift + 5:]), "answers (shift %d)" % shift)
+        f.close()
+
+
+def test_nondefault_stream_and_state_roundtrip():
+    rng = np.random.default_rng(8)
+    a, b = noisy(rng, 30_000), noisy(rng, 30_000)
+    p = oracle.Params(*HOT, 1 << 16)
+    FA = oracle.insert(p, p.empty(), a)
+    FAB = oracle.insert(p, FA.copy(), b)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        f = Filter(*HOT, 1 << 16)
+        da, db = dev(a), dev(b)
+        f.insert(da)
+        f.insert(da)  # idempotent
+    s.synchronize()
+    assert_same(f.get_bits(), FA, "after repeated insert")
+    with torch.cuda.stream(s):
+        f.insert(db)
+        ans = f.query(db)
+    s.synchronize()
+    assert_same(f.get_bits(), FAB, "after second insert")
+    assert ans.cpu().numpy().all()
+    snap = f.get_bits()
+    g = Filter(*HOT, 1 << 16)
+    g.set_bits(snap)
+    assert_same(g.query(a), oracle.query(p, FAB, a), "restored filter answers")
+    f.clear()
+    torch.cuda.synchronize()
+    assert not f.get_bits().any()
+    f.close()
+    g.close()
+
+
+@pytest.mark.parametrize("H", [1, 2, 4, 8])
+def test_all_A_closed_form(H):
+    f = Filter(31, 28, 16, H, 1 << 20)
+    f.insert(dev(np.full(100_000, ord("A"), dtype=np.uint8)))
+    ans = f.query(dev(np.frombuffer(b"A" * 40 + b"C" + b"A" * 40, dtype=np.uint8)))
+    torch.cuda.synchronize()
+    w = f.get_bits()
+    expect = np.zeros_like(w)
+    expect[: min(H, 4)] = 1
+    assert_same(w, expect, "all-A filter")
+    a = ans.cpu().numpy()
+    assert a[:10].all() and a.size == 51
+    f.close()
+
+
+@pytest.mark.parametrize("alphabet", [b"A", b"AC", b"ACGT"])
+def test_colliding_shards_stress(alphabet):
+    """Low-complexity input sends most segments of every workgroup to a few
+    shards: concurrent 64-bit atomic ORs on the same words across XCDs."""
+    rng = np.random.default_rng(len(alphabet))
+    if alphabet == b"ACGT":
+        unit = synth.uniform_acgt(37, 1)
+        seq = np.tile(unit, 60_000)
+    else:
+        seq = np.frombuffer(alphabet, dtype=np.uint8)[rng.integers(0, len(alphabet), 2_000_000)]
+    print("case collide", alphabet, flush=True)
+    check(HOT + (1 << 12,), [(seq, None)], (seq[:100_000], None))
+
+
+def test_rolling_and_generic_agree_on_a_genome():
+    w = synth.in_cache_workload(scale=0.02)  # 2 Mbp genome, 40k reads
+    print("case genome 2 Mbp", flush=True)
+    params = (w["k"], w["s"], w["m"], w["H"], w["bits"])
+    gr = gpu_run(params, [w["insert"]], w["query"], variant="rolling")
+    gg = gpu_run(params, [w["insert"]], w["query"], variant="generic")
+    ob, oa = oracle_run(params, [w["insert"]], w["query"])
+    assert_same(gr[0], ob, "rolling filter")
+    assert_same(gg[0], ob, "generic filter")
+    assert_same(gr[1], oa, "rolling answers")
+    assert_same(gg[1], oa, "generic answers")
