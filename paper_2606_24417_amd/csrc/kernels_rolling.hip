@@ -56,17 +56,114 @@ __device__ __forceinline__ void smer_onehots(uint64_t g, uint64_t (&oh)[4]) {
   for (int t = 0; t < H; ++t) oh[t & 3] |= 1ull << bit_address<H>(g, t);
 }
 
+// How a finished segment reaches the filter.  Global atomics on this GPU run
+// at a fixed ~27 G ops/s whatever the filter size, while plain random 32-byte
+// read-modify-writes run several times faster, so the default insert is two
+// passes over the same segments:
+//   kStore:  read the shard, OR the segment's masks, write it back (plain
+//            accesses; a read-modify-write racing with another one on the
+//            same shard can lose that one's bits, never older bits);
+//   kRepair: read the shard and atomically OR only the bits still missing.
+// After both passes the filter is exactly the OR of every segment, as with
+// kAtomic (the paper's four atomicOr per run head).
+enum InsertMode : int { kAtomic = 0, kStore = 1, kRepair = 2 };
+
+constexpr int kQueueSlots = 3;  // finished segments a lane buffers in LDS
+constexpr int kSubRun = 8;      // k-mers between two drains of the buffer
+
 template <int NW>
-__device__ __forceinline__ void flush_segment(uint64_t *__restrict__ words, uint32_t shard, const uint64_t (&m)[4]) {
+__device__ __forceinline__ void atomic_segment(uint64_t *__restrict__ words, uint32_t shard, const uint64_t (&m)[4]) {
   uint64_t *p = words + 4ull * (uint64_t)shard;
 #pragma unroll
   for (int w = 0; w < NW; ++w) atomic_or64(p + w, m[w]);
 }
 
+// Lane-private LDS buffer of finished segments (structure of arrays, so that
+// the 64 lanes of a wave touch consecutive words).
+template <int WG>
+struct SegmentBuffer {
+  uint32_t shard[kQueueSlots][WG];
+  uint64_t mask[kQueueSlots][4][WG];
+};
+
+template <int NW, int MODE, int WG>
+__device__ __forceinline__ void push_segment(SegmentBuffer<WG> &b, int &n, uint64_t *__restrict__ words,
+                                             uint32_t shard, const uint64_t (&m)[4]) {
+  if (MODE == kAtomic || n >= kQueueSlots) {
+    atomic_segment<NW>(words, shard, m);
+    return;
+  }
+  const int t = threadIdx.x;
+  b.shard[n][t] = shard;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) b.mask[n][w][t] = m[w];
+  ++n;
+}
+
+// Apply the buffered segments: all loads first, then the stores (kStore) or
+// the atomic repairs (kRepair).
+template <int NW, int MODE, int WG>
+__device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uint64_t *__restrict__ words) {
+  if constexpr (MODE != kAtomic) {
+    const int t = threadIdx.x;
+    uint32_t sh[kQueueSlots];
+    uint64_t m[kQueueSlots][4], old[kQueueSlots][4];
+#pragma unroll
+    for (int k = 0; k < kQueueSlots; ++k) {
+      if (k < n) {
+        sh[k] = b.shard[k][t];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) m[k][w] = b.mask[k][w][t];
+        const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)sh[k]);
+        const uint4 lo = p[0], hi = p[1];
+        old[k][0] = ((uint64_t)lo.y << 32) | lo.x;
+        old[k][1] = ((uint64_t)lo.w << 32) | lo.z;
+        old[k][2] = ((uint64_t)hi.y << 32) | hi.x;
+        old[k][3] = ((uint64_t)hi.w << 32) | hi.z;
+      }
+    }
+    if constexpr (MODE == kStore) {
+      // a later buffered segment on the same shard carries the earlier masks,
+      // since its read does not see the earlier write of this lane
+#pragma unroll
+      for (int k = 1; k < kQueueSlots; ++k)
+#pragma unroll
+        for (int j = 0; j < k; ++j)
+          if (k < n && sh[k] == sh[j])
+#pragma unroll
+            for (int w = 0; w < 4; ++w) m[k][w] |= m[j][w];
+#pragma unroll
+      for (int k = 0; k < kQueueSlots; ++k) {
+        if (k < n) {
+          uint64_t v[4];
+#pragma unroll
+          for (int w = 0; w < 4; ++w) v[w] = old[k][w] | m[k][w];
+          uint4 *p = reinterpret_cast<uint4 *>(words + 4ull * (uint64_t)sh[k]);
+          p[0] = make_uint4((uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32));
+          p[1] = make_uint4((uint32_t)v[2], (uint32_t)(v[2] >> 32), (uint32_t)v[3], (uint32_t)(v[3] >> 32));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kQueueSlots; ++k) {
+        if (k < n) {
+          uint64_t *p = words + 4ull * (uint64_t)sh[k];
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            const uint64_t miss = m[k][w] & ~old[k][w];
+            if (miss) atomic_or64(p + w, miss);
+          }
+        }
+      }
+    }
+    n = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Insert: WG lanes x L k-mers per workgroup tile.
 // ---------------------------------------------------------------------------
-template <int K, int S, int M, int H, int L, int WG>
+template <int K, int S, int M, int H, int L, int WG, int MODE>
 __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                             const uint32_t *__restrict__ starts, int aligned16,
                                                             uint64_t *__restrict__ words, uint32_t shard_mask) {
@@ -81,6 +178,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
 
   __shared__ uint32_t s_codes[NGRAN];
   __shared__ uint32_t s_vb[NGRAN];
+  __shared__ SegmentBuffer<(MODE == kAtomic ? 1 : WG)> s_buf;
 
   const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(WG * L);
   stage_granules<WG>(seq, len, base, starts, aligned16 != 0, NGRAN, s_codes, s_vb);
@@ -99,7 +197,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
     }
   }
   const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
-  if (kv == 0) return;
+  if (kv == 0) return;  // no barrier follows
 
   // one-hot masks of s-mers r .. r+Z, OR-ed: A(r).  For Z = 3 the window OR
   // reuses pairs P(j) = oh(j) | oh(j+1): A(r) = P(r) | P(r+2).
@@ -117,6 +215,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
   uint64_t seg[4] = {0, 0, 0, 0};
   uint32_t cur = 0;
   bool open = false;
+  int nbuf = 0;
 
   // van Herk sliding minimum: suf[i] = min(h[qW+i .. qW+W-1]) of block q
   uint64_t suf[W];
@@ -166,12 +265,13 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
         const bool v = (kv >> r) & 1ull;
         const uint32_t sh = (uint32_t)mu & shard_mask;
         const bool cont = open && v && sh == cur;
-        if (open && !cont) flush_segment<NW>(words, cur, seg);
+        if (open && !cont) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
         const uint64_t keep = cont ? ~0ull : 0ull;
 #pragma unroll
         for (int w = 0; w < 4; ++w) seg[w] = (seg[w] & keep) | A[w];
         open = v;
         cur = sh;
+        if (r % kSubRun == kSubRun - 1 && r + 1 < L) drain_segments<NW, MODE>(s_buf, nbuf, words);
       }
     }
     if ((q + 1) * W < L) {
@@ -181,7 +281,8 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
       for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
     }
   }
-  if (open) flush_segment<NW>(words, cur, seg);
+  if (open) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
+  drain_segments<NW, MODE>(s_buf, nbuf, words);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,13 +441,22 @@ constexpr int kInsertWG = 256;
 constexpr int kQueryWG = 256;
 
 template <int K, int S, int M, int H>
-hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, hipStream_t st) {
+hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, int mode, hipStream_t st) {
   if (a.len < (uint64_t)K) return hipSuccess;
   const uint64_t nk = a.len - K + 1;
   const uint64_t tile = (uint64_t)kInsertL * kInsertWG;
   const uint64_t grid = (nk + tile - 1) / tile;
   const int aligned = ((uintptr_t)a.seq & 15u) == 0;
-  hipLaunchKernelGGL((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG>), dim3((unsigned)grid),
+  if (mode == kInsertAtomicMode) {
+    hipLaunchKernelGGL((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kAtomic>), dim3((unsigned)grid),
+                       dim3(kInsertWG), 0, st, a.seq, a.len, a.starts, aligned, words, shard_mask);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kStore>), dim3((unsigned)grid),
+                     dim3(kInsertWG), 0, st, a.seq, a.len, a.starts, aligned, words, shard_mask);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kRepair>), dim3((unsigned)grid),
                      dim3(kInsertWG), 0, st, a.seq, a.len, a.starts, aligned, words, shard_mask);
   return hipGetLastError();
 }
@@ -368,9 +478,9 @@ bool rolling_supported(const Geometry &g) {
   return g.shard_words == 4 && g.nshards <= (1ull << 32) && g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4;
 }
 
-hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st) {
+hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode, hipStream_t st) {
   const uint32_t mask = (uint32_t)(g.nshards - 1);
-  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4) return insert_rolling<31, 28, 16, 4>(words, mask, a, st);
+  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4) return insert_rolling<31, 28, 16, 4>(words, mask, a, mode, st);
   return hipErrorInvalidValue;
 }
 

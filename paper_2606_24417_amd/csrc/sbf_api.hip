@@ -68,6 +68,7 @@ struct sbf_filter {
   hipStream_t stream = nullptr;
   int device = 0;
   int variant = SBF_VARIANT_AUTO;
+  int insert_mode = SBF_INSERT_TWO_PASS;
   uint64_t staging = kDefaultStaging;
   // host entry points: device staging
   Scratch stage_seq, stage_out, stage_off;
@@ -89,7 +90,8 @@ bool use_rolling(const sbf_filter *f) {
   return sbf::rolling_supported(f->g);
 }
 
-hipStream_t pick(const sbf_filter *f, void *stream) { return stream ? (hipStream_t)stream : f->stream; }
+// stream-ordered entry points run on the caller's stream; NULL is HIP's null stream
+hipStream_t pick(const sbf_filter *, void *stream) { return (hipStream_t)stream; }
 
 int grow(Scratch &s, size_t bytes, const char *what) {
   if (s.bytes >= bytes) return SBF_OK;
@@ -110,7 +112,8 @@ int grow(Scratch &s, size_t bytes, const char *what) {
 }
 
 int run_insert(sbf_filter *f, const SeqArgs &a, hipStream_t st) {
-  hipError_t e = use_rolling(f) ? sbf::launch_insert_rolling(f->g, f->words, a, st)
+  const int mode = f->insert_mode == SBF_INSERT_ATOMIC ? sbf::kInsertAtomicMode : sbf::kInsertTwoPassMode;
+  hipError_t e = use_rolling(f) ? sbf::launch_insert_rolling(f->g, f->words, a, mode, st)
                                 : sbf::launch_insert_generic(f->g, f->words, a, st);
   if (e != hipSuccess) return hip_error(e, "insert kernel launch");
   return SBF_OK;
@@ -162,6 +165,8 @@ int set_device(const sbf_filter *f) {
 // Host-sequence insert or query of one record batch, staged in chunks.
 // Chunk boundaries fall on k-mer starts; a chunk carries k-1 extra bases.
 int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out, bool query) {
+  // earlier stream-ordered work on any stream may still use the filter
+  SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
   const uint64_t k = f->g.k;
   const uint64_t total = off[nrec];
   const uint64_t budget = std::max<uint64_t>(f->staging, 4096);
@@ -374,6 +379,40 @@ int sbf_query_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const ui
   return ok();
 }
 
+int sbf_mark_record_starts_dev(const uint64_t *d_off, uint64_t nrec, uint64_t len, uint32_t *d_starts,
+                               void *stream) {
+  if (len == 0) return ok();
+  if (!d_off || !d_starts) return set_error(SBF_E_INVAL, "offsets or record-start bits are NULL");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = sbf::launch_fill_u32(d_starts, (len + 31) / 32, 0u, st);
+  if (e == hipSuccess) e = sbf::launch_mark_record_starts(d_off, nrec, len, d_starts, st);
+  if (e != hipSuccess) return hip_error(e, "record-start marking");
+  return ok();
+}
+
+int sbf_insert_marked_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint32_t *d_starts, void *stream) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len == 0) return ok();
+  if (!d_seq) return set_error(SBF_E_INVAL, "sequence is NULL");
+  if ((rc = set_device(f))) return rc;
+  SeqArgs a{(const uint8_t *)d_seq, len, d_starts, nullptr, 0};
+  if ((rc = run_insert(f, a, pick(f, stream)))) return rc;
+  return ok();
+}
+
+int sbf_query_marked_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint32_t *d_starts, uint8_t *d_out,
+                         void *stream) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len == 0) return ok();
+  if (!d_seq || !d_out) return set_error(SBF_E_INVAL, "sequence or output is NULL");
+  if ((rc = set_device(f))) return rc;
+  SeqArgs a{(const uint8_t *)d_seq, len, d_starts, d_out, len};
+  if ((rc = run_query(f, a, pick(f, stream)))) return rc;
+  return ok();
+}
+
 int sbf_insert_seq(sbf_filter *f, const char *seq, uint64_t len) {
   int rc;
   if ((rc = check_filter(f))) return rc;
@@ -402,6 +441,7 @@ int sbf_query_seq(sbf_filter *f, const char *seq, uint64_t len, uint8_t *out) {
   if ((rc = grow(f->stage_out, budget + 64, "staging buffer"))) return rc;
   hipStream_t st = f->stream;
   (void)off;
+  SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
   for (uint64_t c0 = 0; c0 < n_out; c0 += span) {
     const uint64_t c1 = std::min(n_out, c0 + span);
     const uint64_t e1 = c1 + k - 1;
@@ -453,6 +493,15 @@ int sbf_get_variant(const sbf_filter *f) {
   if (!f) return set_error(SBF_E_INVAL, "filter is NULL");
   ok();
   return use_rolling(f) ? SBF_VARIANT_ROLLING : SBF_VARIANT_GENERIC;
+}
+
+int sbf_set_insert_mode(sbf_filter *f, int mode) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (mode != SBF_INSERT_TWO_PASS && mode != SBF_INSERT_ATOMIC)
+    return set_error(SBF_E_INVAL, "unknown insert mode %d", mode);
+  f->insert_mode = mode;
+  return ok();
 }
 
 int sbf_set_staging_bytes(sbf_filter *f, uint64_t bytes) {

@@ -23,10 +23,15 @@ struct SeqArgs {
   uint64_t n_out;          // query only
 };
 
+// Insert strategies of the rolling kernels: two passes (plain read-modify-write,
+// then an atomic repair of lost bits) or one atomic OR per shard word.
+constexpr int kInsertTwoPassMode = 0;
+constexpr int kInsertAtomicMode = 1;
+
 // Rolling kernels exist for a few compiled parameter sets.
 bool rolling_supported(const Geometry &g);
 
-hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st);
+hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode, hipStream_t st);
 hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);
 hipError_t launch_insert_generic(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st);
 hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);

@@ -23,6 +23,8 @@ SBF_E_DEVICE = -3
 VARIANT_AUTO = 0
 VARIANT_ROLLING = 1
 VARIANT_GENERIC = 2
+INSERT_TWO_PASS = 0
+INSERT_ATOMIC = 1
 
 # every function declared in include/sbf.h, with its ctypes signature
 _vp = ctypes.c_void_p
@@ -48,8 +50,12 @@ SIGNATURES = {
     "sbf_query_batch": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "sbf_insert_batch_dev": (_int, [_vp, _vp, _u64, _vp, _u64, _vp]),
     "sbf_query_batch_dev": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp]),
+    "sbf_mark_record_starts_dev": (_int, [_vp, _u64, _u64, _vp, _vp]),
+    "sbf_insert_marked_dev": (_int, [_vp, _vp, _u64, _vp, _vp]),
+    "sbf_query_marked_dev": (_int, [_vp, _vp, _u64, _vp, _vp, _vp]),
     "sbf_set_variant": (_int, [_vp, _int]),
     "sbf_get_variant": (_int, [_vp]),
+    "sbf_set_insert_mode": (_int, [_vp, _int]),
     "sbf_set_staging_bytes": (_int, [_vp, _u64]),
 }
 
@@ -169,6 +175,9 @@ class Filter:
     def variant(self, v: int):
         _check(lib().sbf_set_variant(self._h, int(v)))
 
+    def set_insert_mode(self, mode: int):
+        _check(lib().sbf_set_insert_mode(self._h, int(mode)))
+
     def set_staging_bytes(self, n: int):
         _check(lib().sbf_set_staging_bytes(self._h, int(n)))
 
@@ -182,7 +191,7 @@ class Filter:
         _check(lib().sbf_set_bits(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size))
 
     def clear(self, stream=None):
-        _check(lib().sbf_clear(self._h, _stream_handle(stream) if stream is not None else None))
+        _check(lib().sbf_clear(self._h, _stream_handle(stream)))
 
     # -- insert / query ------------------------------------------------------------
     def insert(self, seq, offsets=None, stream=None):
@@ -204,6 +213,35 @@ class Filter:
             off = np.ascontiguousarray(offsets, dtype=np.uint64)
             _check(L.sbf_insert_batch(self._h, a.ctypes.data_as(ctypes.c_void_p),
                                       off.ctypes.data_as(ctypes.c_void_p), off.size - 1))
+
+    # -- record batches in two steps (device tensors) ----------------------------
+    @staticmethod
+    def mark_record_starts(offsets, length, starts=None, stream=None):
+        """Record-start bits of a device batch (int32 tensor of ceil(len/32)
+        words, reused by insert_marked / query_marked)."""
+        import torch
+
+        if starts is None:
+            starts = torch.empty((int(length) + 31) // 32, dtype=torch.int32, device=offsets.device)
+        _check(lib().sbf_mark_record_starts_dev(ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
+                                                int(length), ctypes.c_void_p(starts.data_ptr()),
+                                                _stream_handle(stream)))
+        return starts
+
+    def insert_marked(self, seq, starts=None, stream=None):
+        _check(lib().sbf_insert_marked_dev(self._h, ctypes.c_void_p(seq.data_ptr()), seq.numel(),
+                                           ctypes.c_void_p(starts.data_ptr() if starts is not None else None),
+                                           _stream_handle(stream)))
+
+    def query_marked(self, seq, starts=None, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty(seq.numel(), dtype=torch.uint8, device=seq.device)
+        _check(lib().sbf_query_marked_dev(self._h, ctypes.c_void_p(seq.data_ptr()), seq.numel(),
+                                          ctypes.c_void_p(starts.data_ptr() if starts is not None else None),
+                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
 
     def query(self, seq, offsets=None, out=None, stream=None):
         """Answers as uint8 0/1.  A single sequence gives len-k+1 answers; a

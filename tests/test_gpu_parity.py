@@ -273,3 +273,41 @@ def test_rolling_and_generic_agree_on_a_genome():
     assert_same(gg[0], ob, "generic filter")
     assert_same(gr[1], oa, "rolling answers")
     assert_same(gg[1], oa, "generic answers")
+
+
+def test_marked_batch_entry_points_match_batch_form():
+    """Marking record starts once and reusing them gives the batch results."""
+    rng = np.random.default_rng(9)
+    ins = random_batch(rng, 400, 500, 0.001)
+    q = random_batch(rng, 300, 400)
+    ob, oa = oracle_run(HOT + (1 << 16,), [ins], q)
+    f = Filter(*HOT, 1 << 16)
+    d_ins, d_ioff = dev(ins[0]), dev(ins[1].view(np.int64))
+    d_q, d_qoff = dev(q[0]), dev(q[1].view(np.int64))
+    st_i = f.mark_record_starts(d_ioff, ins[0].size)
+    st_q = f.mark_record_starts(d_qoff, q[0].size)
+    f.insert_marked(d_ins, st_i)
+    f.insert_marked(d_ins, st_i)
+    out = f.query_marked(d_q, st_q)
+    torch.cuda.synchronize()
+    assert_same(f.get_bits(), ob, "filter words")
+    assert_same(out.cpu().numpy(), oa, "answers")
+    f.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("bits", [1 << 10, 1 << 16, 1 << 24])
+def test_insert_modes_match_oracle(mode, bits):
+    """Two-pass insert (plain read-modify-write, then atomic repair) and the
+    one-atomic-per-word insert give the oracle's filter, also when many
+    segments hit few shards (small filters force concurrent updates)."""
+    rng = np.random.default_rng(bits + mode)
+    ins = noisy(rng, 300_000, 0.001)
+    p = oracle.Params(*HOT, bits)
+    F = oracle.insert(p, p.empty(), ins)
+    f = Filter(*HOT, bits)
+    f.set_insert_mode(mode)
+    f.insert(dev(ins))
+    torch.cuda.synchronize()
+    assert_same(f.get_bits(), F, "filter words (mode %d)" % mode)
+    f.close()
