@@ -128,6 +128,31 @@ def cpu_baseline(w, budget_s: float = 12.0):
                           k_ins / t_ins, k_q / max(t_q, 1e-9))}
 
 
+def segments_per_kmer(p, batch, sample_bases: int = 4_000_000) -> float:
+    """Super-k-mer segments per k-mer position (one shard access each), counted
+    by the oracle on the records covering the first sample_bases bases and on
+    as many from the middle of the batch."""
+    import oracle
+
+    seq, off = batch
+    nrec = off.size - 1
+    segs = kmers = 0
+    for r0 in (0, nrec // 2):
+        r1 = r0
+        while r1 < nrec and int(off[r1] - off[r0]) < sample_bases // 2:
+            r1 += 1
+        r1 = max(r1, r0 + 1)
+        a, b = int(off[r0]), int(off[r1])
+        sub_off = off[r0:r1 + 1] - off[r0]
+        part = seq[a:b]
+        if sub_off.size == 2 and part.size > sample_bases // 2:
+            part = part[: sample_bases // 2]
+            sub_off = np.array([0, part.size], dtype=np.uint64)
+        segs += oracle.count_segments(p, part, sub_off)
+        kmers += kmer_positions(sub_off, p.k)
+    return segs / max(1, kmers)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,7 +251,8 @@ def main():
 
         p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
         seqs = w["query"] if dom == "query" else w["insert"]
-        nseg = oracle.count_segments(p, seqs[0], seqs[1])
+        seg_per_kmer = segments_per_kmer(p, seqs)
+        nseg = seg_per_kmer * dom_kmers
         per_seg = 32 if dom == "query" else 64
         nbytes = nseg * per_seg + seqs[0].size * (2 if dom == "query" else 1)
         achieved = nbytes / (dom_ms * 1e-3) / 1e9

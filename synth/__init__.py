@@ -77,11 +77,14 @@ def substitute(seq: np.ndarray, rate: float, rng: np.random.Generator) -> np.nda
     out = seq.copy()
     if rate <= 0 or seq.size == 0:
         return out
-    pos = np.flatnonzero(rng.random(seq.size) < rate)
-    if pos.size:
-        code = np.searchsorted(ACGT, out[pos])
-        code = (code + rng.integers(1, 4, pos.size)) % 4
-        out[pos] = ACGT[code]
+    step = 1 << 24
+    for a in range(0, seq.size, step):
+        part = out[a:a + step]
+        pos = np.flatnonzero(rng.random(part.size, dtype=np.float32) < rate)
+        if pos.size:
+            code = np.searchsorted(ACGT, part[pos])
+            code = (code + rng.integers(1, 4, pos.size)) % 4
+            part[pos] = ACGT[code]
     return out
 
 
@@ -145,21 +148,20 @@ def sample_reads(seq: np.ndarray, off: np.ndarray, n: int, lengths, seed,
     roff = np.zeros(n + 1, dtype=np.uint64)
     roff[1:] = np.cumsum(lens)
     out = np.empty(int(roff[-1]), dtype=np.uint8)
-    for a in range(0, n, 1 << 18):
-        b = min(n, a + (1 << 18))
+    # contig chosen with probability proportional to its number of start positions
+    room = np.maximum(clen[None, :] - lens[:, None] + 1, 0).astype(np.float64)
+    cum = np.cumsum(room, axis=1)
+    ci = (cum < rng.random(n)[:, None] * cum[:, -1:]).sum(axis=1)
+    ci = np.minimum(ci, clen.size - 1)
+    start = off[ci].astype(np.int64) + (rng.random(n) * room[np.arange(n), ci]).astype(np.int64)
+    ro = roff.astype(np.int64)
+    per = max(1, (1 << 24) // max(1, int(lens.mean())))
+    for a in range(0, n, per):
+        b = min(n, a + per)
         L = lens[a:b]
-        room = np.maximum(clen[None, :] - L[:, None] + 1, 0)
-        # contig chosen with probability proportional to its start positions
-        cw = room.astype(np.float64)
-        cw /= cw.sum(axis=1, keepdims=True)
-        cum = np.cumsum(cw, axis=1)
-        ci = (cum < rng.random(b - a)[:, None]).sum(axis=1)
-        ci = np.minimum(ci, clen.size - 1)
-        start = off[ci].astype(np.int64) + (rng.random(b - a) * room[np.arange(b - a), ci]).astype(np.int64)
-        idx = np.repeat(start - roff[a:b].astype(np.int64), L) + np.arange(int(L.sum())) + int(roff[a])
-        chunk = seq[idx]
-        out[int(roff[a]):int(roff[b])] = substitute(chunk, sub_rate, rng)
-    return out, roff
+        idx = np.repeat(start[a:b] - ro[a:b], L) + np.arange(int(ro[b] - ro[a])) + ro[a]
+        out[ro[a]:ro[b]] = seq[idx]
+    return substitute(out, sub_rate, rng), roff
 
 
 def random_reads(n: int, lengths, seed, gc: float = 0.41):
