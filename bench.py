@@ -153,6 +153,34 @@ def segments_per_kmer(p, batch, sample_bases: int = 4_000_000) -> float:
     return segs / max(1, kmers)
 
 
+def run_probes(sizes_mib, copy_only=False):
+    """Random shard-access and copy rates from libsbf_probe.so (include/sbf_probe.h)."""
+    import ctypes
+
+    from paper_2606_24417_amd import build
+
+    L = ctypes.CDLL(build.PROBE_LIB)
+    fn = L.sbf_probe_random_access
+    fn.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                   ctypes.POINTER(ctypes.c_double)]
+    names = ["read32", "rmw32", "atomic4", "atomic1", "copy"]
+    out = []
+    modes = [4] if copy_only else [0, 1, 2, 3, 4]
+    for mib in sizes_mib:
+        row = {"buffer_mib": mib}
+        for mode in modes:
+            rate, ms = ctypes.c_double(), ctypes.c_double()
+            rc = fn(int(mib) << 20, mode, 1 << 26, ctypes.byref(rate), ctypes.byref(ms))
+            if rc != 0:
+                raise SystemExit("probe failed rc=%d (mode %d, %d MiB)" % (rc, mode, mib))
+            key = names[mode] + ("_GBps" if mode == 4 else "_Gops")
+            row[key] = round(rate.value / 1e9, 2)
+            row[names[mode] + "_ms"] = round(ms.value, 4)
+        out.append(row)
+        print(json.dumps(row), flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,11 +190,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")
     ap.add_argument("--bits", type=int, default=0, help="filter size override (default: the workload's)")
+    ap.add_argument("--probe", action="store_true", help="print random-access and copy roofline probes, then exit")
+    ap.add_argument("--probe-copy-mib", type=int, default=0,
+                    help="run only the streaming-copy probe on a buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    if args.probe:
+        run_probes([2, 32, 256, 1024, 8192])
+        return
+    if args.probe_copy_mib:
+        run_probes([args.probe_copy_mib], copy_only=True)
+        return
 
     import torch
 

@@ -11,6 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsbf.so")
 SOURCES = ["sbf_api.hip", "kernels_rolling.hip", "kernels_generic.hip"]
+PROBE_LIB = os.path.join(PKG, "libsbf_probe.so")
+PROBE_SOURCES = ["probe_random_access.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -29,21 +31,27 @@ def hipcc() -> str:
     return path if os.path.exists(path) else "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _compile(out: str, sources, verbose: bool) -> str:
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [hipcc()] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-o", tmp]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
+    cmd += [os.path.join(CSRC, s) for s in sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
+    text = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
-        sys.stderr.write(out + "\n")
-        raise RuntimeError("hipcc failed building libsbf.so")
-    if verbose and out.strip():
-        print(out)
-    os.replace(tmp, LIB)
-    return LIB
+        sys.stderr.write(text + "\n")
+        raise RuntimeError("hipcc failed building %s" % os.path.basename(out))
+    if verbose and text.strip():
+        print(text)
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Build libsbf.so (the filter) and libsbf_probe.so (roofline probes)."""
+    _compile(PROBE_LIB, PROBE_SOURCES, verbose)
+    return _compile(LIB, SOURCES, verbose)
 
 
 if __name__ == "__main__":

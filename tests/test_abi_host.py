@@ -11,10 +11,11 @@ import pytest
 from conftest import ROOT
 
 HEADER = os.path.join(ROOT, "include", "sbf.h")
+PROBE_HEADER = os.path.join(ROOT, "include", "sbf_probe.h")
 
 
-def header_functions():
-    text = open(HEADER).read()
+def header_functions(path=HEADER):
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(sbf_[a-z_0-9]+)\s*\(", text)))
 
@@ -67,6 +68,26 @@ def test_null_filter_calls_fail_cleanly(L):
                L.sbf_set_variant(None, 0), L.sbf_set_staging_bytes(None, 1 << 20)):
         assert rc == sbf.SBF_E_INVAL
         assert sbf.last_error()[0] == sbf.SBF_E_INVAL
+
+
+def test_probe_library_exports_its_header():
+    from paper_2606_24417_amd import build
+
+    if not os.path.exists(build.PROBE_LIB):
+        pytest.skip("libsbf_probe.so not built")
+    L = ctypes.CDLL(build.PROBE_LIB)
+    names = header_functions(PROBE_HEADER)
+    assert names == ["sbf_probe_random_access"]
+    for n in names:
+        assert hasattr(L, n)
+    # argument checks happen before any device call
+    fn = L.sbf_probe_random_access
+    fn.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                   ctypes.POINTER(ctypes.c_double)]
+    a, b = ctypes.c_double(), ctypes.c_double()
+    assert fn(3 << 20, 0, 1 << 20, ctypes.byref(a), ctypes.byref(b)) == -1  # not a power of two
+    assert fn(1 << 20, 9, 1 << 20, ctypes.byref(a), ctypes.byref(b)) == -1  # bad mode
+    assert fn(1 << 20, 0, 1 << 20, None, None) == -1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
