@@ -190,6 +190,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")
     ap.add_argument("--bits", type=int, default=0, help="filter size override (default: the workload's)")
+    ap.add_argument("--query-mode", type=int, default=0, help="0 lane-sequential, 1 leader load + broadcast, 2 every lane loads")
+    ap.add_argument("--insert-mode", type=int, default=0, help="0 two-pass, 1 atomic")
+    ap.add_argument("--launch", type=str, default="0,0",
+                    help="persistent workgroups per CU for insert,query (0 = one workgroup per tile)")
+    ap.add_argument("--autotune", action="store_true", help="run the library autotuner on the workload first")
     ap.add_argument("--probe", action="store_true", help="print random-access and copy roofline probes, then exit")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="run only the streaming-copy probe on a buffer of this many MiB (counter calibration)")
@@ -232,6 +237,15 @@ def main():
     f = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
     if args.variant:
         f.variant = args.variant
+    f.set_query_mode(args.query_mode)
+    f.set_insert_mode(args.insert_mode)
+    li, lq = (int(x) for x in args.launch.split(","))
+    f.set_launch(li, lq)
+    tuned = None
+    if args.autotune:
+        report = f.autotune(d_ins, d_ioff, d_q, d_qoff)
+        print(report, file=sys.stderr, flush=True)
+        tuned = f.get_launch()
     ins_starts = Filter.mark_record_starts(d_ioff, ins.size)
     q_starts = Filter.mark_record_starts(d_qoff, qs.size)
     torch.cuda.synchronize()
@@ -324,6 +338,7 @@ def main():
         "insert_ms_median": round(float(np.median(ins_ms)), 4),
         "query_ms_median": round(float(np.median(q_ms)), 4),
         "query_present": n_q_valid,
+        "settings": f.get_launch(),
         "roofline": roof,
         "cpu_baseline": None,
     }

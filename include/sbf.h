@@ -166,6 +166,60 @@ int sbf_get_variant(const sbf_filter *f); /* the family in effect (1 or 2) */
 #define SBF_INSERT_ATOMIC 1
 int sbf_set_insert_mode(sbf_filter *f, int mode);
 
+/* How the rolling query kernel is organised:
+ *   SBF_QUERY_LANE (default): each lane walks 32 consecutive k-mers, builds
+ *     the mask of each k-mer's (k-s+1)*H bits from its s-mers, loads the
+ *     k-mer's shard and tests the mask two k-mers later; consecutive k-mers
+ *     of one super-k-mer reuse the cached shard;
+ *   SBF_QUERY_LEADER: a first pass stores shards and bit addresses in LDS, a
+ *     second tests one k-mer per lane; the first lane of each run of equal
+ *     shards loads the 32-byte shard and the run's other lanes receive it by
+ *     a cross-lane permute (Algorithm 2's leader load and shuffle);
+ *   SBF_QUERY_DIRECT: as SBF_QUERY_LEADER, but every valid lane loads.
+ * All three give the same answers. */
+#define SBF_QUERY_LANE 0
+#define SBF_QUERY_LEADER 1
+#define SBF_QUERY_DIRECT 2
+int sbf_set_query_mode(sbf_filter *f, int mode);
+
+/* Launch shape of the rolling kernels: 0 workgroups per CU launches one
+ * workgroup per tile; n > 0 launches a persistent grid of n workgroups per
+ * compute unit that take tiles from a device work-queue counter until the
+ * batch is done.  Insert and query are set separately (n <= 32).  The
+ * counters live per stream, so persistent calls on one stream are ordered;
+ * sbf_get_launch reads the settings back (any pointer may be NULL). */
+int sbf_set_launch(sbf_filter *f, uint32_t insert_wgs_per_cu, uint32_t query_wgs_per_cu);
+int sbf_get_launch(const sbf_filter *f, uint32_t *insert_wgs_per_cu, uint32_t *query_wgs_per_cu, int *insert_mode,
+                   int *query_mode);
+
+/* Batched form: capture, once, a HIP graph that optionally clears the filter,
+ * marks the record starts of an insert batch and of a query batch, inserts
+ * the first and queries the second (device batches as in
+ * sbf_insert_batch_dev / sbf_query_batch_dev; either may be NULL), with the
+ * kernel organisation and launch shape in effect at creation.  The graph
+ * owns its scratch (record-start bits, work-queue counters) and refers to
+ * the caller's buffers and to f, which must outlive it.  sbf_graph_launch
+ * replays it on stream (NULL = HIP's null stream); replays on one stream are
+ * ordered, replays on different streams must not overlap.  Returns NULL on
+ * error (see sbf_last_error). */
+typedef struct sbf_graph sbf_graph;
+sbf_graph *sbf_graph_create(sbf_filter *f, int clear_first, const char *d_ins, uint64_t ins_len,
+                            const uint64_t *d_ins_off, uint64_t ins_nrec, const char *d_q, uint64_t q_len,
+                            const uint64_t *d_q_off, uint64_t q_nrec, uint8_t *d_out);
+int sbf_graph_launch(sbf_graph *g, void *stream);
+void sbf_graph_destroy(sbf_graph *g);
+
+/* Autotuner: on the given device insert and query batches, time every insert
+ * strategy and query organisation with one workgroup per tile and with
+ * persistent grids of 1, 2, 4 and 8 workgroups per CU (median of three runs
+ * after a warm-up; inserts go to a scratch filter of the same geometry, so f
+ * is not modified), then apply the fastest settings to f.  A text report of
+ * every timing is written to report (NUL-terminated, truncated to
+ * report_len; may be NULL).  Synchronous. */
+int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec,
+                 const char *d_q, uint64_t q_len, const uint64_t *d_q_off, uint64_t q_nrec, char *report,
+                 uint64_t report_len);
+
 /* Bytes of sequence the host entry points stage on the device per chunk
  * (default 256 MiB; at least 4096).  Inputs longer than this are processed in
  * chunks that overlap by k-1 bases. */

@@ -4,7 +4,7 @@ super-k-mer sharding, atomic-OR insert, leader-load query) behind the C ABI
 of include/sbf.h, with a thin ctypes binding."""
 
 from .sbf import (SBF_E_DEVICE, SBF_E_INVAL, SBF_E_NOMEM, SBF_OK, VARIANT_AUTO, VARIANT_GENERIC,
-                  VARIANT_ROLLING, Filter, SBFError, last_error, lib)
+                  VARIANT_ROLLING, Filter, Graph, SBFError, last_error, lib)
 
-__all__ = ["Filter", "SBFError", "lib", "last_error", "SBF_OK", "SBF_E_INVAL", "SBF_E_NOMEM", "SBF_E_DEVICE",
+__all__ = ["Filter", "Graph", "SBFError", "lib", "last_error", "SBF_OK", "SBF_E_INVAL", "SBF_E_NOMEM", "SBF_E_DEVICE",
            "VARIANT_AUTO", "VARIANT_ROLLING", "VARIANT_GENERIC"]

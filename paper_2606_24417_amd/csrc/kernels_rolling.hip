@@ -32,6 +32,27 @@ namespace {
 template <int K, int L>
 constexpr int lane_granules() { return (L + K - 1 + 15) / 16 + 1; }
 
+// Tile scheduler.  A plain launch runs tile blockIdx.x once; a persistent
+// launch (counter not null) keeps taking the next tile index from a device
+// counter (the work queue) until all ntiles are taken.  The decision is
+// uniform over the workgroup, so every wave leaves the loop together.
+struct TileQueue {
+  uint32_t *counter;
+  uint32_t ntiles;
+};
+
+__device__ __forceinline__ bool next_tile(const TileQueue &q, uint32_t *s_slot, bool first, uint64_t &tile) {
+  if (q.counter == nullptr) {
+    tile = blockIdx.x;
+    return first;
+  }
+  __syncthreads();  // every lane has read the previous slot
+  if (threadIdx.x == 0) *s_slot = atomicAdd(q.counter, 1u);
+  __syncthreads();
+  tile = *s_slot;
+  return tile < q.ntiles;
+}
+
 template <int M>
 __device__ __forceinline__ uint32_t mmer_at(const uint32_t *a, int j) {
   static_assert(M >= 1 && M <= 16, "m-mers of the rolling kernels fit 32 bits");
@@ -166,7 +187,7 @@ __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uin
 template <int K, int S, int M, int H, int L, int WG, int MODE>
 __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                             const uint32_t *__restrict__ starts, int aligned16,
-                                                            uint64_t *__restrict__ words, uint32_t shard_mask) {
+                                                            uint64_t *__restrict__ words, uint32_t shard_mask, TileQueue tq) {
   constexpr int W = K - M + 1;
   constexpr int Z = K - S;
   constexpr int GPL = L / 16;
@@ -180,109 +201,113 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
   __shared__ uint32_t s_vb[NGRAN];
   __shared__ SegmentBuffer<(MODE == kAtomic ? 1 : WG)> s_buf;
 
-  const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)(WG * L);
-  stage_granules<WG>(seq, len, base, starts, aligned16 != 0, NGRAN, s_codes, s_vb);
-  __syncthreads();
+  __shared__ uint32_t s_next_tile;
+  uint64_t tile;
+  for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
+  const uint64_t base = (uint64_t)tile * (uint64_t)(WG * L);
+    stage_granules<WG>(seq, len, base, starts, aligned16 != 0, NGRAN, s_codes, s_vb);
+    __syncthreads();
 
-  const int g0 = threadIdx.x * GPL;
-  uint32_t a[NGW];
-  uint64_t vbits = 0, sbits = 0;
-#pragma unroll
-  for (int i = 0; i < NGW; ++i) {
-    a[i] = s_codes[g0 + i];
-    if (i < 4) {
-      const uint32_t vb = s_vb[g0 + i];
-      vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
-      sbits |= (uint64_t)(vb >> 16) << (16 * i);
-    }
-  }
-  const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
-  if (kv == 0) return;  // no barrier follows
-
-  // one-hot masks of s-mers r .. r+Z, OR-ed: A(r).  For Z = 3 the window OR
-  // reuses pairs P(j) = oh(j) | oh(j+1): A(r) = P(r) | P(r+2).
-  uint64_t oh[L + Z][4];
-  uint64_t pr[L + Z][4];
-#pragma unroll
-  for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
-  if constexpr (Z == 3) {
-#pragma unroll
-    for (int j = 0; j + 1 < Z; ++j)
-#pragma unroll
-      for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
-  }
-
-  uint64_t seg[4] = {0, 0, 0, 0};
-  uint32_t cur = 0;
-  bool open = false;
-  int nbuf = 0;
-
-  // van Herk sliding minimum: suf[i] = min(h[qW+i .. qW+W-1]) of block q
-  uint64_t suf[W];
-  {
-    uint64_t hb[W];
-#pragma unroll
-    for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
-    suf[W - 1] = hb[W - 1];
-#pragma unroll
-    for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
-  }
-
-#pragma unroll
-  for (int q = 0; q * W < L; ++q) {
-    uint64_t hb[W];
-    uint64_t pre = ~0ull;
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-      const int r = q * W + i;
-      if (r < L) {
-        uint64_t mu;
-        if (i == 0) {
-          mu = suf[0];
-        } else {
-          hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
-          pre = umin64(pre, hb[i - 1]);
-          mu = umin64(suf[i], pre);
-        }
-        // newest s-mer of k-mer r
-        smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
-        uint64_t A[4];
-        if constexpr (Z == 3) {
-#pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
-            A[w] = pr[r][w] | pr[r + 2][w];
-          }
-        } else {
-#pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            uint64_t x = oh[r][w];
-#pragma unroll
-            for (int j = 1; j <= Z; ++j) x |= oh[r + j][w];
-            A[w] = x;
-          }
-        }
-        const bool v = (kv >> r) & 1ull;
-        const uint32_t sh = (uint32_t)mu & shard_mask;
-        const bool cont = open && v && sh == cur;
-        if (open && !cont) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
-        const uint64_t keep = cont ? ~0ull : 0ull;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) seg[w] = (seg[w] & keep) | A[w];
-        open = v;
-        cur = sh;
-        if (r % kSubRun == kSubRun - 1 && r + 1 < L) drain_segments<NW, MODE>(s_buf, nbuf, words);
+    const int g0 = threadIdx.x * GPL;
+    uint32_t a[NGW];
+    uint64_t vbits = 0, sbits = 0;
+  #pragma unroll
+    for (int i = 0; i < NGW; ++i) {
+      a[i] = s_codes[g0 + i];
+      if (i < 4) {
+        const uint32_t vb = s_vb[g0 + i];
+        vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
+        sbits |= (uint64_t)(vb >> 16) << (16 * i);
       }
     }
-    if ((q + 1) * W < L) {
-      hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+    const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
+    if (kv == 0) continue;
+
+    // one-hot masks of s-mers r .. r+Z, OR-ed: A(r).  For Z = 3 the window OR
+    // reuses pairs P(j) = oh(j) | oh(j+1): A(r) = P(r) | P(r+2).
+    uint64_t oh[L + Z][4];
+    uint64_t pr[L + Z][4];
+  #pragma unroll
+    for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
+    if constexpr (Z == 3) {
+  #pragma unroll
+      for (int j = 0; j + 1 < Z; ++j)
+  #pragma unroll
+        for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
+    }
+
+    uint64_t seg[4] = {0, 0, 0, 0};
+    uint32_t cur = 0;
+    bool open = false;
+    int nbuf = 0;
+
+    // van Herk sliding minimum: suf[i] = min(h[qW+i .. qW+W-1]) of block q
+    uint64_t suf[W];
+    {
+      uint64_t hb[W];
+  #pragma unroll
+      for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
       suf[W - 1] = hb[W - 1];
-#pragma unroll
+  #pragma unroll
       for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
     }
+
+  #pragma unroll
+    for (int q = 0; q * W < L; ++q) {
+      uint64_t hb[W];
+      uint64_t pre = ~0ull;
+  #pragma unroll
+      for (int i = 0; i < W; ++i) {
+        const int r = q * W + i;
+        if (r < L) {
+          uint64_t mu;
+          if (i == 0) {
+            mu = suf[0];
+          } else {
+            hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+            pre = umin64(pre, hb[i - 1]);
+            mu = umin64(suf[i], pre);
+          }
+          // newest s-mer of k-mer r
+          smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
+          uint64_t A[4];
+          if constexpr (Z == 3) {
+  #pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
+              A[w] = pr[r][w] | pr[r + 2][w];
+            }
+          } else {
+  #pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              uint64_t x = oh[r][w];
+  #pragma unroll
+              for (int j = 1; j <= Z; ++j) x |= oh[r + j][w];
+              A[w] = x;
+            }
+          }
+          const bool v = (kv >> r) & 1ull;
+          const uint32_t sh = (uint32_t)mu & shard_mask;
+          const bool cont = open && v && sh == cur;
+          if (open && !cont) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
+          const uint64_t keep = cont ? ~0ull : 0ull;
+  #pragma unroll
+          for (int w = 0; w < 4; ++w) seg[w] = (seg[w] & keep) | A[w];
+          open = v;
+          cur = sh;
+          if (r % kSubRun == kSubRun - 1 && r + 1 < L) drain_segments<NW, MODE>(s_buf, nbuf, words);
+        }
+      }
+      if ((q + 1) * W < L) {
+        hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+        suf[W - 1] = hb[W - 1];
+  #pragma unroll
+        for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+      }
+    }
+    if (open) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
+    drain_segments<NW, MODE>(s_buf, nbuf, words);
   }
-  if (open) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
-  drain_segments<NW, MODE>(s_buf, nbuf, words);
 }
 
 // ---------------------------------------------------------------------------
@@ -304,7 +329,7 @@ template <int K, int S, int M, int H, int WG, bool SHARE>
 __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                            const uint32_t *__restrict__ starts, int aligned16,
                                                            const uint64_t *__restrict__ words, uint32_t shard_mask,
-                                                           uint8_t *__restrict__ out, uint64_t n_out) {
+                                                           uint8_t *__restrict__ out, uint64_t n_out, TileQueue tq) {
   constexpr int L = 16;
   constexpr int TILE = WG * L;
   constexpr int W = K - M + 1;
@@ -320,156 +345,345 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
   __shared__ Pack s_bits[TILE + Z];
   __shared__ uint32_t s_kv[WG];
 
-  const uint64_t base = (uint64_t)blockIdx.x * (uint64_t)TILE;
-  stage_granules<WG>(seq, len, base, starts, aligned16 != 0, NGRAN, s_codes, s_vb);
-  __syncthreads();
+  __shared__ uint32_t s_next_tile;
+  uint64_t tile;
+  for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
+  const uint64_t base = (uint64_t)tile * (uint64_t)TILE;
+    stage_granules<WG>(seq, len, base, starts, aligned16 != 0, NGRAN, s_codes, s_vb);
+    __syncthreads();
 
-  // ---- phase 1: lane t owns k-mers 16t .. 16t+15 of the tile ----
-  {
-    const int t = threadIdx.x;
+    // ---- phase 1: lane t owns k-mers 16t .. 16t+15 of the tile ----
+    {
+      const int t = threadIdx.x;
+      uint32_t a[NGW];
+      uint64_t vbits = 0, sbits = 0;
+  #pragma unroll
+      for (int i = 0; i < NGW; ++i) {
+        a[i] = s_codes[t + i];
+        if (i < 4) {
+          const uint32_t vb = s_vb[t + i];
+          vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
+          sbits |= (uint64_t)(vb >> 16) << (16 * i);
+        }
+      }
+      s_kv[t] = (uint32_t)(kmer_valid_mask<K>(vbits, sbits) & 0xFFFFull);
+
+      uint64_t suf[W];
+      {
+        uint64_t hb[W];
+  #pragma unroll
+        for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
+        suf[W - 1] = hb[W - 1];
+  #pragma unroll
+        for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+      }
+  #pragma unroll
+      for (int q = 0; q * W < L; ++q) {
+        uint64_t hb[W];
+        uint64_t pre = ~0ull;
+  #pragma unroll
+        for (int i = 0; i < W; ++i) {
+          const int r = q * W + i;
+          if (r < L) {
+            uint64_t mu;
+            if (i == 0) {
+              mu = suf[0];
+            } else {
+              hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+              pre = umin64(pre, hb[i - 1]);
+              mu = umin64(suf[i], pre);
+            }
+            s_shard[t * L + r] = (uint32_t)mu & shard_mask;
+          }
+        }
+        if ((q + 1) * W < L) {
+          hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+          suf[W - 1] = hb[W - 1];
+  #pragma unroll
+          for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+        }
+      }
+  #pragma unroll
+      for (int j = 0; j < L; ++j) s_bits[t * L + j] = pack_bit_addresses<H>(smer_hash(smer_at<S>(a, j)));
+      if (t == WG - 1) {
+  #pragma unroll
+        for (int j = L; j < L + Z; ++j) s_bits[t * L + j] = pack_bit_addresses<H>(smer_hash(smer_at<S>(a, j)));
+      }
+    }
+    __syncthreads();
+
+    // ---- phase 2: one k-mer per lane, consecutive k-mers across the wave ----
+    const int lane = threadIdx.x & 63;
+  #pragma unroll 2
+    for (int i = 0; i < L; ++i) {
+      const int q = i * WG + threadIdx.x;
+      const bool v = (s_kv[q >> 4] >> (q & 15)) & 1u;
+      const uint32_t shard = s_shard[q];
+      uint32_t wd[8];
+      if constexpr (SHARE) {
+        const int qp = q > 0 ? q - 1 : 0;
+        const bool pv = q > 0 && ((s_kv[qp >> 4] >> (qp & 15)) & 1u);
+        const bool head = v && (lane == 0 || !pv || s_shard[qp] != shard);
+        const uint64_t heads = __ballot(head);
+        const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+        const int leader = upto ? 63 - __clzll((long long)upto) : lane;
+        if (head) {
+          const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)shard);
+          const uint4 lo = p[0], hi = p[1];
+          wd[0] = lo.x; wd[1] = lo.y; wd[2] = lo.z; wd[3] = lo.w;
+          wd[4] = hi.x; wd[5] = hi.y; wd[6] = hi.z; wd[7] = hi.w;
+        } else {
+  #pragma unroll
+          for (int j = 0; j < 8; ++j) wd[j] = 0;
+        }
+  #pragma unroll
+        for (int j = 0; j < 8; ++j) wd[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(leader << 2, (int)wd[j]);
+      } else {
+        if (v) {
+          const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)shard);
+          const uint4 lo = p[0], hi = p[1];
+          wd[0] = lo.x; wd[1] = lo.y; wd[2] = lo.z; wd[3] = lo.w;
+          wd[4] = hi.x; wd[5] = hi.y; wd[6] = hi.z; wd[7] = hi.w;
+        } else {
+  #pragma unroll
+          for (int j = 0; j < 8; ++j) wd[j] = 0;
+        }
+      }
+      uint64_t w4[4];
+  #pragma unroll
+      for (int w = 0; w < 4; ++w) w4[w] = ((uint64_t)wd[2 * w + 1] << 32) | wd[2 * w];
+      uint32_t acc = 0xFFFFFFFFu;
+  #pragma unroll
+      for (int p = 0; p <= Z; ++p) {
+        const Pack b = s_bits[q + p];
+  #pragma unroll
+        for (int t = 0; t < H; ++t) acc &= (uint32_t)(w4[t & 3] >> ((uint32_t)(b >> (8 * t)) & 63u));
+      }
+      const uint64_t pos = base + (uint64_t)q;
+      if (pos < n_out) out[pos] = v ? (uint8_t)(acc & 1u) : (uint8_t)0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Query, lane-sequential: each lane walks L consecutive k-mers like the insert
+// kernel.  For k-mer r it forms the OR A(r) of the one-hot masks of its z+1
+// s-mers (the same pair trick), issues the two 16-byte loads of its shard, and
+// D k-mers later tests (A(r) & ~shard) == 0, so the load latency overlaps the
+// hashing of the next k-mers.  Consecutive k-mers of a lane share their shard
+// while they stay in one super-k-mer, so the repeated loads hit the cache.
+// Answers are packed four per register and written as 16-byte stores.
+// ---------------------------------------------------------------------------
+template <int K, int S, int M, int H, int L, int WG, int D>
+__global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+                                                        const uint32_t *__restrict__ starts, int aligned16,
+                                                        const uint64_t *__restrict__ words, uint32_t shard_mask,
+                                                        uint8_t *__restrict__ out, uint64_t n_out, TileQueue tq) {
+  constexpr int W = K - M + 1;
+  constexpr int Z = K - S;
+  constexpr int GPL = L / 16;
+  constexpr int NGW = lane_granules<K, L>();
+  constexpr int NGRAN = (WG - 1) * GPL + NGW;
+  static_assert(L % 16 == 0 && L + K - 1 <= 64, "a lane's bases fit one 64-bit validity word");
+  static_assert(D >= 1 && D < L, "test distance");
+
+  __shared__ uint32_t s_codes[NGRAN];
+  __shared__ uint32_t s_vb[NGRAN];
+
+  __shared__ uint32_t s_next_tile;
+  uint64_t tile;
+  for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
+  const uint64_t base = (uint64_t)tile * (uint64_t)(WG * L);
+    stage_granules<WG>(seq, len, base, starts, aligned16 != 0, NGRAN, s_codes, s_vb);
+    __syncthreads();
+
+    const int g0 = threadIdx.x * GPL;
     uint32_t a[NGW];
     uint64_t vbits = 0, sbits = 0;
-#pragma unroll
+  #pragma unroll
     for (int i = 0; i < NGW; ++i) {
-      a[i] = s_codes[t + i];
+      a[i] = s_codes[g0 + i];
       if (i < 4) {
-        const uint32_t vb = s_vb[t + i];
+        const uint32_t vb = s_vb[g0 + i];
         vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
         sbits |= (uint64_t)(vb >> 16) << (16 * i);
       }
     }
-    s_kv[t] = (uint32_t)(kmer_valid_mask<K>(vbits, sbits) & 0xFFFFull);
+    const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
+    const uint64_t pos0 = base + (uint64_t)threadIdx.x * L;
+    uint32_t res[L / 4];
+  #pragma unroll
+    for (int i = 0; i < L / 4; ++i) res[i] = 0;
 
-    uint64_t suf[W];
-    {
-      uint64_t hb[W];
-#pragma unroll
-      for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
-      suf[W - 1] = hb[W - 1];
-#pragma unroll
-      for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
-    }
-#pragma unroll
-    for (int q = 0; q * W < L; ++q) {
-      uint64_t hb[W];
-      uint64_t pre = ~0ull;
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        const int r = q * W + i;
-        if (r < L) {
-          uint64_t mu;
-          if (i == 0) {
-            mu = suf[0];
-          } else {
-            hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
-            pre = umin64(pre, hb[i - 1]);
-            mu = umin64(suf[i], pre);
-          }
-          s_shard[t * L + r] = (uint32_t)mu & shard_mask;
-        }
+    if (kv != 0) {
+      uint64_t oh[L + Z][4];
+      uint64_t pr[L + Z][4];
+      uint64_t need[L][4];     // A(r), kept D k-mers
+      uint64_t got[L][4];      // shard of k-mer r, kept D k-mers
+  #pragma unroll
+      for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
+      if constexpr (Z == 3) {
+  #pragma unroll
+        for (int j = 0; j + 1 < Z; ++j)
+  #pragma unroll
+          for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
       }
-      if ((q + 1) * W < L) {
-        hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+      uint64_t suf[W];
+      {
+        uint64_t hb[W];
+  #pragma unroll
+        for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
         suf[W - 1] = hb[W - 1];
-#pragma unroll
+  #pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
       }
-    }
-#pragma unroll
-    for (int j = 0; j < L; ++j) s_bits[t * L + j] = pack_bit_addresses<H>(smer_hash(smer_at<S>(a, j)));
-    if (t == WG - 1) {
-#pragma unroll
-      for (int j = L; j < L + Z; ++j) s_bits[t * L + j] = pack_bit_addresses<H>(smer_hash(smer_at<S>(a, j)));
-    }
-  }
-  __syncthreads();
-
-  // ---- phase 2: one k-mer per lane, consecutive k-mers across the wave ----
-  const int lane = threadIdx.x & 63;
-#pragma unroll 2
-  for (int i = 0; i < L; ++i) {
-    const int q = i * WG + threadIdx.x;
-    const bool v = (s_kv[q >> 4] >> (q & 15)) & 1u;
-    const uint32_t shard = s_shard[q];
-    uint32_t wd[8];
-    if constexpr (SHARE) {
-      const int qp = q > 0 ? q - 1 : 0;
-      const bool pv = q > 0 && ((s_kv[qp >> 4] >> (qp & 15)) & 1u);
-      const bool head = v && (lane == 0 || !pv || s_shard[qp] != shard);
-      const uint64_t heads = __ballot(head);
-      const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-      const int leader = upto ? 63 - __clzll((long long)upto) : lane;
-      if (head) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)shard);
-        const uint4 lo = p[0], hi = p[1];
-        wd[0] = lo.x; wd[1] = lo.y; wd[2] = lo.z; wd[3] = lo.w;
-        wd[4] = hi.x; wd[5] = hi.y; wd[6] = hi.z; wd[7] = hi.w;
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) wd[j] = 0;
+      auto test = [&](int r) {
+        uint32_t miss = 0;
+  #pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint64_t m = need[r][w] & ~got[r][w];
+          miss |= (uint32_t)m | (uint32_t)(m >> 32);
+        }
+        const uint32_t present = (miss == 0 && ((kv >> r) & 1ull)) ? 1u : 0u;
+        res[r >> 2] |= present << (8 * (r & 3));
+      };
+  #pragma unroll
+      for (int q = 0; q * W < L; ++q) {
+        uint64_t hb[W];
+        uint64_t pre = ~0ull;
+  #pragma unroll
+        for (int i = 0; i < W; ++i) {
+          const int r = q * W + i;
+          if (r < L) {
+            uint64_t mu;
+            if (i == 0) {
+              mu = suf[0];
+            } else {
+              hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+              pre = umin64(pre, hb[i - 1]);
+              mu = umin64(suf[i], pre);
+            }
+            const uint32_t sh = (uint32_t)mu & shard_mask;
+            const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)sh);
+            const uint4 lo = p[0], hi = p[1];
+            got[r][0] = ((uint64_t)lo.y << 32) | lo.x;
+            got[r][1] = ((uint64_t)lo.w << 32) | lo.z;
+            got[r][2] = ((uint64_t)hi.y << 32) | hi.x;
+            got[r][3] = ((uint64_t)hi.w << 32) | hi.z;
+            smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
+            if constexpr (Z == 3) {
+  #pragma unroll
+              for (int w = 0; w < 4; ++w) {
+                pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
+                need[r][w] = pr[r][w] | pr[r + 2][w];
+              }
+            } else {
+  #pragma unroll
+              for (int w = 0; w < 4; ++w) {
+                uint64_t x = oh[r][w];
+  #pragma unroll
+                for (int j = 1; j <= Z; ++j) x |= oh[r + j][w];
+                need[r][w] = x;
+              }
+            }
+            if (r >= D) test(r - D);
+          }
+        }
+        if ((q + 1) * W < L) {
+          hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+          suf[W - 1] = hb[W - 1];
+  #pragma unroll
+          for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+        }
       }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) wd[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(leader << 2, (int)wd[j]);
+  #pragma unroll
+      for (int r = L - D; r < L; ++r) test(r);
+    }
+    if (pos0 + L <= n_out) {
+      uint4 *o = reinterpret_cast<uint4 *>(out + pos0);
+  #pragma unroll
+      for (int i = 0; i < L / 16; ++i) o[i] = make_uint4(res[4 * i], res[4 * i + 1], res[4 * i + 2], res[4 * i + 3]);
     } else {
-      if (v) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)shard);
-        const uint4 lo = p[0], hi = p[1];
-        wd[0] = lo.x; wd[1] = lo.y; wd[2] = lo.z; wd[3] = lo.w;
-        wd[4] = hi.x; wd[5] = hi.y; wd[6] = hi.z; wd[7] = hi.w;
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) wd[j] = 0;
-      }
+  #pragma unroll
+      for (int r = 0; r < L; ++r)
+        if (pos0 + r < n_out) out[pos0 + r] = (uint8_t)(res[r >> 2] >> (8 * (r & 3)));
     }
-    uint64_t w4[4];
-#pragma unroll
-    for (int w = 0; w < 4; ++w) w4[w] = ((uint64_t)wd[2 * w + 1] << 32) | wd[2 * w];
-    uint32_t acc = 0xFFFFFFFFu;
-#pragma unroll
-    for (int p = 0; p <= Z; ++p) {
-      const Pack b = s_bits[q + p];
-#pragma unroll
-      for (int t = 0; t < H; ++t) acc &= (uint32_t)(w4[t & 3] >> ((uint32_t)(b >> (8 * t)) & 63u));
-    }
-    const uint64_t pos = base + (uint64_t)q;
-    if (pos < n_out) out[pos] = v ? (uint8_t)(acc & 1u) : (uint8_t)0;
   }
 }
 
 constexpr int kInsertL = 32;
 constexpr int kInsertWG = 256;
 constexpr int kQueryWG = 256;
+constexpr int kQueryLaneL = 32;
+constexpr int kQueryLaneWG = 256;
+constexpr int kQueryLaneD = 2;
+
+// Grid of a launch over ntiles tiles: one workgroup per tile, or a persistent
+// grid that takes tiles from the queue counter `slot` (reset first).
+hipError_t tile_grid(uint64_t ntiles, const LaunchShape &ls, int slot, hipStream_t st, TileQueue &tq,
+                     unsigned &grid) {
+  tq.counter = nullptr;
+  tq.ntiles = (uint32_t)ntiles;
+  grid = (unsigned)ntiles;
+  if (ls.queue != nullptr && ls.persistent_wgs != 0) {
+    tq.counter = ls.queue + slot;
+    grid = (unsigned)(ntiles < ls.persistent_wgs ? ntiles : ls.persistent_wgs);
+    return launch_fill_u32(tq.counter, 1, 0u, st);
+  }
+  return hipSuccess;
+}
+
+#define SBF_LAUNCH_TILES(KERNEL, WGS, NTILES, SLOT, ...)                      \
+  do {                                                                          \
+    TileQueue tq_;                                                              \
+    unsigned grid_;                                                             \
+    hipError_t e_ = tile_grid((NTILES), ls, (SLOT), st, tq_, grid_);            \
+    if (e_ != hipSuccess) return e_;                                            \
+    hipLaunchKernelGGL(KERNEL, dim3(grid_), dim3(WGS), 0, st, __VA_ARGS__, tq_); \
+    e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess) return e_;                                            \
+  } while (0)
 
 template <int K, int S, int M, int H>
-hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, int mode, hipStream_t st) {
+hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, int mode, const LaunchShape &ls,
+                          hipStream_t st) {
   if (a.len < (uint64_t)K) return hipSuccess;
   const uint64_t nk = a.len - K + 1;
   const uint64_t tile = (uint64_t)kInsertL * kInsertWG;
-  const uint64_t grid = (nk + tile - 1) / tile;
+  const uint64_t ntiles = (nk + tile - 1) / tile;
   const int aligned = ((uintptr_t)a.seq & 15u) == 0;
   if (mode == kInsertAtomicMode) {
-    hipLaunchKernelGGL((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kAtomic>), dim3((unsigned)grid),
-                       dim3(kInsertWG), 0, st, a.seq, a.len, a.starts, aligned, words, shard_mask);
-    return hipGetLastError();
+    SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kAtomic>), kInsertWG, ntiles, 0,
+                     a.seq, a.len, a.starts, aligned, words, shard_mask);
+    return hipSuccess;
   }
-  hipLaunchKernelGGL((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kStore>), dim3((unsigned)grid),
-                     dim3(kInsertWG), 0, st, a.seq, a.len, a.starts, aligned, words, shard_mask);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kRepair>), dim3((unsigned)grid),
-                     dim3(kInsertWG), 0, st, a.seq, a.len, a.starts, aligned, words, shard_mask);
-  return hipGetLastError();
+  SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kStore>), kInsertWG, ntiles, 0, a.seq,
+                   a.len, a.starts, aligned, words, shard_mask);
+  SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kRepair>), kInsertWG, ntiles, 1, a.seq,
+                   a.len, a.starts, aligned, words, shard_mask);
+  return hipSuccess;
 }
 
 template <int K, int S, int M, int H>
-hipError_t query_rolling(const uint64_t *words, uint32_t shard_mask, const SeqArgs &a, hipStream_t st) {
+hipError_t query_rolling(const uint64_t *words, uint32_t shard_mask, const SeqArgs &a, int mode,
+                         const LaunchShape &ls, hipStream_t st) {
   if (a.n_out == 0) return hipSuccess;
-  const uint64_t tile = 16ull * kQueryWG;
-  const uint64_t grid = (a.n_out + tile - 1) / tile;
   const int aligned = ((uintptr_t)a.seq & 15u) == 0;
-  hipLaunchKernelGGL((query_rolling_kernel<K, S, M, H, kQueryWG, true>), dim3((unsigned)grid), dim3(kQueryWG), 0,
-                     st, a.seq, a.len, a.starts, aligned, words, shard_mask, a.out, a.n_out);
-  return hipGetLastError();
+  if (mode == kQueryLaneMode) {
+    const uint64_t tile = (uint64_t)kQueryLaneL * kQueryLaneWG;
+    SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, kQueryLaneL, kQueryLaneWG, kQueryLaneD>), kQueryLaneWG,
+                     (a.n_out + tile - 1) / tile, 2, a.seq, a.len, a.starts, aligned, words, shard_mask, a.out,
+                     a.n_out);
+    return hipSuccess;
+  }
+  const uint64_t tile = 16ull * kQueryWG;
+  if (mode == kQueryLeaderMode)
+    SBF_LAUNCH_TILES((query_rolling_kernel<K, S, M, H, kQueryWG, true>), kQueryWG, (a.n_out + tile - 1) / tile, 2,
+                     a.seq, a.len, a.starts, aligned, words, shard_mask, a.out, a.n_out);
+  else
+    SBF_LAUNCH_TILES((query_rolling_kernel<K, S, M, H, kQueryWG, false>), kQueryWG, (a.n_out + tile - 1) / tile, 2,
+                     a.seq, a.len, a.starts, aligned, words, shard_mask, a.out, a.n_out);
+  return hipSuccess;
 }
 
 }  // namespace
@@ -478,15 +692,19 @@ bool rolling_supported(const Geometry &g) {
   return g.shard_words == 4 && g.nshards <= (1ull << 32) && g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4;
 }
 
-hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode, hipStream_t st) {
+hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode,
+                                 const LaunchShape &ls, hipStream_t st) {
   const uint32_t mask = (uint32_t)(g.nshards - 1);
-  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4) return insert_rolling<31, 28, 16, 4>(words, mask, a, mode, st);
+  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4)
+    return insert_rolling<31, 28, 16, 4>(words, mask, a, mode, ls, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st) {
+hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, int mode,
+                                const LaunchShape &ls, hipStream_t st) {
   const uint32_t mask = (uint32_t)(g.nshards - 1);
-  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4) return query_rolling<31, 28, 16, 4>(words, mask, a, st);
+  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4)
+    return query_rolling<31, 28, 16, 4>(words, mask, a, mode, ls, st);
   return hipErrorInvalidValue;
 }
 

@@ -69,12 +69,18 @@ struct sbf_filter {
   int device = 0;
   int variant = SBF_VARIANT_AUTO;
   int insert_mode = SBF_INSERT_TWO_PASS;
+  int query_mode = SBF_QUERY_LANE;
+  uint32_t insert_wgs_per_cu = 0;  // 0: one workgroup per tile; else persistent
+  uint32_t query_wgs_per_cu = 0;
+  int num_cus = 1;
   uint64_t staging = kDefaultStaging;
   // host entry points: device staging
   Scratch stage_seq, stage_out, stage_off;
   // record-start bits, one buffer per stream
   std::mutex mu;
   std::unordered_map<hipStream_t, Scratch> starts;
+  // work-queue counters of persistent launches, one set per stream
+  std::unordered_map<hipStream_t, Scratch> queues;
 };
 
 namespace {
@@ -111,17 +117,62 @@ int grow(Scratch &s, size_t bytes, const char *what) {
   return SBF_OK;
 }
 
-int run_insert(sbf_filter *f, const SeqArgs &a, hipStream_t st) {
+// Launch shape for a pass on stream st (queue counters allocated on first use
+// of a stream), unless the caller supplies its own (graph capture).
+int launch_shape(sbf_filter *f, uint32_t wgs_per_cu, hipStream_t st, sbf::LaunchShape &ls) {
+  ls.queue = nullptr;
+  ls.persistent_wgs = 0;
+  if (wgs_per_cu == 0) return SBF_OK;
+  Scratch *s;
+  {
+    std::lock_guard<std::mutex> lk(f->mu);
+    s = &f->queues[st];
+  }
+  int rc = grow(*s, 256, "work-queue counters");
+  if (rc) return rc;
+  ls.queue = (uint32_t *)s->ptr;
+  ls.persistent_wgs = wgs_per_cu * (uint32_t)f->num_cus;
+  return SBF_OK;
+}
+
+int run_insert(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::LaunchShape *given = nullptr) {
   const int mode = f->insert_mode == SBF_INSERT_ATOMIC ? sbf::kInsertAtomicMode : sbf::kInsertTwoPassMode;
-  hipError_t e = use_rolling(f) ? sbf::launch_insert_rolling(f->g, f->words, a, mode, st)
-                                : sbf::launch_insert_generic(f->g, f->words, a, st);
+  hipError_t e;
+  if (use_rolling(f)) {
+    sbf::LaunchShape ls;
+    if (given) {
+      ls = *given;
+      ls.persistent_wgs = f->insert_wgs_per_cu * (uint32_t)f->num_cus;
+    } else {
+      int rc = launch_shape(f, f->insert_wgs_per_cu, st, ls);
+      if (rc) return rc;
+    }
+    e = sbf::launch_insert_rolling(f->g, f->words, a, mode, ls, st);
+  } else {
+    e = sbf::launch_insert_generic(f->g, f->words, a, st);
+  }
   if (e != hipSuccess) return hip_error(e, "insert kernel launch");
   return SBF_OK;
 }
 
-int run_query(sbf_filter *f, const SeqArgs &a, hipStream_t st) {
-  hipError_t e = use_rolling(f) ? sbf::launch_query_rolling(f->g, f->words, a, st)
-                                : sbf::launch_query_generic(f->g, f->words, a, st);
+int run_query(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::LaunchShape *given = nullptr) {
+  const int mode = f->query_mode == SBF_QUERY_DIRECT   ? sbf::kQueryDirectMode
+                   : f->query_mode == SBF_QUERY_LEADER ? sbf::kQueryLeaderMode
+                                                       : sbf::kQueryLaneMode;
+  hipError_t e;
+  if (use_rolling(f)) {
+    sbf::LaunchShape ls;
+    if (given) {
+      ls = *given;
+      ls.persistent_wgs = f->query_wgs_per_cu * (uint32_t)f->num_cus;
+    } else {
+      int rc = launch_shape(f, f->query_wgs_per_cu, st, ls);
+      if (rc) return rc;
+    }
+    e = sbf::launch_query_rolling(f->g, f->words, a, mode, ls, st);
+  } else {
+    e = sbf::launch_query_generic(f->g, f->words, a, st);
+  }
   if (e != hipSuccess) return hip_error(e, "query kernel launch");
   return SBF_OK;
 }
@@ -246,6 +297,7 @@ sbf_filter *sbf_create(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t 
   f->g.shard_words = 4;
   f->g.nshards = next_pow2(std::max<uint64_t>(1, (bits + 255) / 256));
   hipError_t e = hipGetDevice(&f->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&f->num_cus, hipDeviceAttributeMultiprocessorCount, f->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     hip_error(e, "stream creation");
@@ -279,6 +331,8 @@ void sbf_destroy(sbf_filter *f) {
   (void)hipSetDevice(f->device);
   (void)hipDeviceSynchronize();
   for (auto &kv : f->starts)
+    if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  for (auto &kv : f->queues)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   if (f->stage_seq.ptr) (void)hipFree(f->stage_seq.ptr);
   if (f->stage_out.ptr) (void)hipFree(f->stage_out.ptr);
@@ -504,11 +558,285 @@ int sbf_set_insert_mode(sbf_filter *f, int mode) {
   return ok();
 }
 
+int sbf_set_query_mode(sbf_filter *f, int mode) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (mode != SBF_QUERY_LANE && mode != SBF_QUERY_LEADER && mode != SBF_QUERY_DIRECT)
+    return set_error(SBF_E_INVAL, "unknown query mode %d", mode);
+  f->query_mode = mode;
+  return ok();
+}
+
+int sbf_set_launch(sbf_filter *f, uint32_t insert_wgs_per_cu, uint32_t query_wgs_per_cu) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (insert_wgs_per_cu > 32 || query_wgs_per_cu > 32)
+    return set_error(SBF_E_INVAL, "at most 32 persistent workgroups per CU");
+  f->insert_wgs_per_cu = insert_wgs_per_cu;
+  f->query_wgs_per_cu = query_wgs_per_cu;
+  return ok();
+}
+
+int sbf_get_launch(const sbf_filter *f, uint32_t *insert_wgs_per_cu, uint32_t *query_wgs_per_cu, int *insert_mode,
+                   int *query_mode) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (insert_wgs_per_cu) *insert_wgs_per_cu = f->insert_wgs_per_cu;
+  if (query_wgs_per_cu) *query_wgs_per_cu = f->query_wgs_per_cu;
+  if (insert_mode) *insert_mode = f->insert_mode;
+  if (query_mode) *query_mode = f->query_mode;
+  return ok();
+}
+
 int sbf_set_staging_bytes(sbf_filter *f, uint64_t bytes) {
   int rc;
   if ((rc = check_filter(f))) return rc;
   if (bytes < 4096) return set_error(SBF_E_INVAL, "staging must be at least 4096 bytes");
   f->staging = bytes;
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form: a HIP graph of one insert batch and one query batch, and the
+// autotuner of launch shapes and kernel organisation.
+// ---------------------------------------------------------------------------
+struct sbf_graph {
+  sbf_filter *f = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  Scratch starts_ins, starts_q, queue;
+};
+
+namespace {
+
+void free_scratch(Scratch &s) {
+  if (s.ptr) (void)hipFree(s.ptr);
+  s.ptr = nullptr;
+  s.bytes = 0;
+}
+
+void graph_release(sbf_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  free_scratch(g->starts_ins);
+  free_scratch(g->starts_q);
+  free_scratch(g->queue);
+  delete g;
+}
+
+// fill + mark record starts into s (allocated before any capture)
+int mark_into(Scratch &s, const uint64_t *d_off, uint64_t nrec, uint64_t len, hipStream_t st, const uint32_t **out) {
+  *out = nullptr;
+  if (nrec < 2 || len == 0) return SBF_OK;
+  const uint64_t nw = (len + 31) / 32;
+  hipError_t e = sbf::launch_fill_u32((uint32_t *)s.ptr, nw, 0u, st);
+  if (e == hipSuccess) e = sbf::launch_mark_record_starts(d_off, nrec, len, (uint32_t *)s.ptr, st);
+  if (e != hipSuccess) return hip_error(e, "record-start marking");
+  *out = (const uint32_t *)s.ptr;
+  return SBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbf_graph *sbf_graph_create(sbf_filter *f, int clear_first, const char *d_ins, uint64_t ins_len,
+                            const uint64_t *d_ins_off, uint64_t ins_nrec, const char *d_q, uint64_t q_len,
+                            const uint64_t *d_q_off, uint64_t q_nrec, uint8_t *d_out) {
+  if (check_filter(f)) return nullptr;
+  if ((d_ins && ins_len && (!d_ins_off || ins_nrec == 0)) || (d_q && q_len && (!d_q_off || q_nrec == 0 || !d_out))) {
+    set_error(SBF_E_INVAL, "batch without offsets, records or output");
+    return nullptr;
+  }
+  if (set_device(f)) return nullptr;
+  sbf_graph *g = new (std::nothrow) sbf_graph;
+  if (!g) {
+    set_error(SBF_E_NOMEM, "host allocation of the graph object");
+    return nullptr;
+  }
+  g->f = f;
+  const bool do_ins = d_ins && ins_len, do_q = d_q && q_len;
+  int rc = grow(g->queue, 256, "work-queue counters");
+  if (!rc && do_ins && ins_nrec > 1) rc = grow(g->starts_ins, (ins_len + 31) / 32 * 4, "record-start bits");
+  if (!rc && do_q && q_nrec > 1) rc = grow(g->starts_q, (q_len + 31) / 32 * 4, "record-start bits");
+  hipError_t e = hipSuccess;
+  if (!rc) {
+    e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) rc = hip_error(e, "capture stream");
+  }
+  if (rc) {
+    graph_release(g);
+    return nullptr;
+  }
+  e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    hip_error(e, "graph capture");
+    graph_release(g);
+    return nullptr;
+  }
+  sbf::LaunchShape ls{(uint32_t *)g->queue.ptr, 0};
+  if (clear_first) {
+    e = sbf::launch_fill_u64(f->words, sbf_num_words(f), 0ull, g->cap);
+    if (e != hipSuccess) rc = hip_error(e, "clear kernel launch");
+  }
+  const uint32_t *st_ins = nullptr, *st_q = nullptr;
+  if (!rc && do_ins) rc = mark_into(g->starts_ins, d_ins_off, ins_nrec, ins_len, g->cap, &st_ins);
+  if (!rc && do_q) rc = mark_into(g->starts_q, d_q_off, q_nrec, q_len, g->cap, &st_q);
+  if (!rc && do_ins) {
+    SeqArgs a{(const uint8_t *)d_ins, ins_len, st_ins, nullptr, 0};
+    rc = run_insert(f, a, g->cap, &ls);
+  }
+  if (!rc && do_q) {
+    SeqArgs a{(const uint8_t *)d_q, q_len, st_q, d_out, q_len};
+    rc = run_query(f, a, g->cap, &ls);
+  }
+  e = hipStreamEndCapture(g->cap, &g->graph);
+  if (!rc && e != hipSuccess) rc = hip_error(e, "graph capture");
+  if (!rc) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = hip_error(e, "graph instantiation");
+  }
+  if (rc) {
+    graph_release(g);
+    return nullptr;
+  }
+  ok();
+  return g;
+}
+
+int sbf_graph_launch(sbf_graph *g, void *stream) {
+  if (!g) return set_error(SBF_E_INVAL, "graph is NULL");
+  int rc;
+  if ((rc = set_device(g->f))) return rc;
+  SBF_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+  return ok();
+}
+
+void sbf_graph_destroy(sbf_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->f->device);
+  (void)hipDeviceSynchronize();
+  graph_release(g);
+}
+
+int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec,
+                 const char *d_q, uint64_t q_len, const uint64_t *d_q_off, uint64_t q_nrec, char *report,
+                 uint64_t report_len) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (!d_ins || !d_ins_off || !ins_len || !ins_nrec || !d_q || !d_q_off || !q_len || !q_nrec)
+    return set_error(SBF_E_INVAL, "autotuning needs an insert batch and a query batch");
+  if ((rc = set_device(f))) return rc;
+  std::string rep;
+  auto line = [&](const char *fmt, auto... args) {
+    char buf[256];
+    snprintf(buf, sizeof buf, fmt, args...);
+    rep += buf;
+  };
+  if (!use_rolling(f)) {
+    line("generic kernels: nothing to tune\n");
+  } else {
+    // a scratch filter of the same geometry takes the inserts
+    sbf_filter *t = sbf_create(f->g.k, f->g.s, f->g.m, f->g.H, sbf_num_bits(f));
+    if (!t) return g_err;
+    Scratch si, sq, out;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t st = t->stream;
+    rc = grow(si, (ins_len + 31) / 32 * 4, "record-start bits");
+    if (!rc) rc = grow(sq, (q_len + 31) / 32 * 4, "record-start bits");
+    if (!rc) rc = grow(out, q_len, "autotune answers");
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+      rc = set_error(SBF_E_DEVICE, "event creation");
+    const uint32_t *st_i = nullptr, *st_q = nullptr;
+    if (!rc) rc = mark_into(si, d_ins_off, ins_nrec, ins_len, st, &st_i);
+    if (!rc) rc = mark_into(sq, d_q_off, q_nrec, q_len, st, &st_q);
+    const uint32_t shapes[] = {0, 1, 2, 4, 8};
+    auto time_it = [&](bool insert, float &ms_out) -> int {
+      float best[3];
+      for (int rep_i = 0; rep_i < 4; ++rep_i) {
+        if (insert) {
+          hipError_t e = sbf::launch_fill_u64(t->words, sbf_num_words(t), 0ull, st);
+          if (e != hipSuccess) return hip_error(e, "clear kernel launch");
+        }
+        if (hipEventRecord(e0, st) != hipSuccess) return set_error(SBF_E_DEVICE, "event record");
+        int r2 = insert ? run_insert(t, SeqArgs{(const uint8_t *)d_ins, ins_len, st_i, nullptr, 0}, st)
+                        : run_query(t, SeqArgs{(const uint8_t *)d_q, q_len, st_q, (uint8_t *)out.ptr, q_len}, st);
+        if (r2) return r2;
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+          return set_error(SBF_E_DEVICE, "event timing");
+        if (rep_i > 0) best[rep_i - 1] = ms;
+      }
+      std::sort(best, best + 3);
+      ms_out = best[1];
+      return SBF_OK;
+    };
+    float best_ins = 1e30f, best_q = 1e30f;
+    int bi_mode = SBF_INSERT_TWO_PASS, bq_mode = SBF_QUERY_LANE;
+    uint32_t bi_shape = 0, bq_shape = 0;
+    for (int mode : {SBF_INSERT_TWO_PASS, SBF_INSERT_ATOMIC}) {
+      for (uint32_t sh : shapes) {
+        if (rc) break;
+        t->insert_mode = mode;
+        t->insert_wgs_per_cu = sh;
+        float ms;
+        rc = time_it(true, ms);
+        if (rc) break;
+        line("insert %-8s workgroups/CU %u%s: %.4f ms\n", mode == SBF_INSERT_ATOMIC ? "atomic" : "two-pass", sh,
+             sh ? "" : " (one per tile)", ms);
+        if (ms < best_ins) {
+          best_ins = ms;
+          bi_mode = mode;
+          bi_shape = sh;
+        }
+      }
+    }
+    for (int mode : {SBF_QUERY_LANE, SBF_QUERY_LEADER, SBF_QUERY_DIRECT}) {
+      for (uint32_t sh : shapes) {
+        if (rc) break;
+        t->query_mode = mode;
+        t->query_wgs_per_cu = sh;
+        float ms;
+        rc = time_it(false, ms);
+        if (rc) break;
+        line("query  %-8s workgroups/CU %u%s: %.4f ms\n",
+             mode == SBF_QUERY_LANE ? "lane" : mode == SBF_QUERY_LEADER ? "leader" : "direct", sh,
+             sh ? "" : " (one per tile)", ms);
+        if (ms < best_q) {
+          best_q = ms;
+          bq_mode = mode;
+          bq_shape = sh;
+        }
+      }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    free_scratch(si);
+    free_scratch(sq);
+    free_scratch(out);
+    sbf_destroy(t);
+    if (rc) return rc;
+    f->insert_mode = bi_mode;
+    f->insert_wgs_per_cu = bi_shape;
+    f->query_mode = bq_mode;
+    f->query_wgs_per_cu = bq_shape;
+    line("best insert: %s, workgroups/CU %u (%.4f ms)\n", bi_mode == SBF_INSERT_ATOMIC ? "atomic" : "two-pass",
+         bi_shape, best_ins);
+    line("best query: %s, workgroups/CU %u (%.4f ms)\n",
+         bq_mode == SBF_QUERY_LANE ? "lane" : bq_mode == SBF_QUERY_LEADER ? "leader" : "direct", bq_shape, best_q);
+  }
+  if (report && report_len) {
+    const size_t n = std::min<size_t>(rep.size(), report_len - 1);
+    memcpy(report, rep.data(), n);
+    report[n] = 0;
+  }
   return ok();
 }
 

@@ -28,11 +28,29 @@ struct SeqArgs {
 constexpr int kInsertTwoPassMode = 0;
 constexpr int kInsertAtomicMode = 1;
 
+// Rolling query kernels: lane-sequential (each lane tests its own run of
+// k-mers), or two phases with one k-mer per lane in the second, where the
+// first lane of each run of equal shards loads and broadcasts (leader) or
+// every lane loads (direct).
+constexpr int kQueryLaneMode = 0;
+constexpr int kQueryLeaderMode = 1;
+constexpr int kQueryDirectMode = 2;
+
 // Rolling kernels exist for a few compiled parameter sets.
 bool rolling_supported(const Geometry &g);
 
-hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode, hipStream_t st);
-hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);
+// Launch shape of the rolling kernels: one workgroup per tile, or a
+// persistent grid of persistent_wgs workgroups that take tiles from device
+// counters (queue: three u32 work-queue counters, one per pass).
+struct LaunchShape {
+  uint32_t *queue;
+  uint32_t persistent_wgs;
+};
+
+hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode,
+                                 const LaunchShape &ls, hipStream_t st);
+hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, int mode,
+                                const LaunchShape &ls, hipStream_t st);
 hipError_t launch_insert_generic(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st);
 hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);
 

@@ -25,6 +25,9 @@ VARIANT_ROLLING = 1
 VARIANT_GENERIC = 2
 INSERT_TWO_PASS = 0
 INSERT_ATOMIC = 1
+QUERY_LANE = 0
+QUERY_LEADER = 1
+QUERY_DIRECT = 2
 
 # every function declared in include/sbf.h, with its ctypes signature
 _vp = ctypes.c_void_p
@@ -56,7 +59,14 @@ SIGNATURES = {
     "sbf_set_variant": (_int, [_vp, _int]),
     "sbf_get_variant": (_int, [_vp]),
     "sbf_set_insert_mode": (_int, [_vp, _int]),
+    "sbf_set_query_mode": (_int, [_vp, _int]),
     "sbf_set_staging_bytes": (_int, [_vp, _u64]),
+    "sbf_set_launch": (_int, [_vp, _u32, _u32]),
+    "sbf_get_launch": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sbf_graph_create": (_vp, [_vp, _int, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp]),
+    "sbf_graph_launch": (_int, [_vp, _vp]),
+    "sbf_graph_destroy": (None, [_vp]),
+    "sbf_autotune": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64]),
 }
 
 _lib = None
@@ -178,6 +188,30 @@ class Filter:
     def set_insert_mode(self, mode: int):
         _check(lib().sbf_set_insert_mode(self._h, int(mode)))
 
+    def set_query_mode(self, mode: int):
+        _check(lib().sbf_set_query_mode(self._h, int(mode)))
+
+    def set_launch(self, insert_wgs_per_cu: int = 0, query_wgs_per_cu: int = 0):
+        """0 = one workgroup per tile; n > 0 = persistent grid of n workgroups per CU."""
+        _check(lib().sbf_set_launch(self._h, int(insert_wgs_per_cu), int(query_wgs_per_cu)))
+
+    def get_launch(self) -> dict:
+        iw, qw = ctypes.c_uint32(), ctypes.c_uint32()
+        im, qm = ctypes.c_int(), ctypes.c_int()
+        _check(lib().sbf_get_launch(self._h, ctypes.byref(iw), ctypes.byref(qw), ctypes.byref(im), ctypes.byref(qm)))
+        return {"insert_wgs_per_cu": iw.value, "query_wgs_per_cu": qw.value, "insert_mode": im.value,
+                "query_mode": qm.value}
+
+    def autotune(self, ins, ins_off, q, q_off) -> str:
+        """Time launch shapes and kernel organisations on device batches and keep
+        the fastest (sbf_autotune).  Returns the timing report."""
+        buf = ctypes.create_string_buffer(8192)
+        _check(lib().sbf_autotune(self._h, ctypes.c_void_p(ins.data_ptr()), ins.numel(),
+                                  ctypes.c_void_p(ins_off.data_ptr()), ins_off.numel() - 1,
+                                  ctypes.c_void_p(q.data_ptr()), q.numel(), ctypes.c_void_p(q_off.data_ptr()),
+                                  q_off.numel() - 1, buf, len(buf)))
+        return buf.value.decode()
+
     def set_staging_bytes(self, n: int):
         _check(lib().sbf_set_staging_bytes(self._h, int(n)))
 
@@ -275,3 +309,36 @@ class Filter:
         _check(L.sbf_query_batch(self._h, a.ctypes.data_as(ctypes.c_void_p), off.ctypes.data_as(ctypes.c_void_p),
                                  off.size - 1, res.ctypes.data_as(ctypes.c_void_p)))
         return res
+
+
+class Graph:
+    """A captured HIP graph of one insert batch and/or one query batch on a
+    filter (sbf_graph_create).  Device tensors; the caller keeps them alive."""
+
+    def __init__(self, f: Filter, ins=None, ins_off=None, q=None, q_off=None, out=None, clear_first=False):
+        def ptr(t):
+            return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+        h = lib().sbf_graph_create(f.handle, int(bool(clear_first)), ptr(ins), ins.numel() if ins is not None else 0,
+                                   ptr(ins_off), ins_off.numel() - 1 if ins_off is not None else 0, ptr(q),
+                                   q.numel() if q is not None else 0, ptr(q_off),
+                                   q_off.numel() - 1 if q_off is not None else 0, ptr(out))
+        if not h:
+            code, msg = last_error()
+            raise SBFError(code, msg)
+        self._h = ctypes.c_void_p(h)
+        self._keep = (f, ins, ins_off, q, q_off, out)
+
+    def launch(self, stream=None):
+        _check(lib().sbf_graph_launch(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sbf_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

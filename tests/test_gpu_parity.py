@@ -311,3 +311,82 @@ def test_insert_modes_match_oracle(mode, bits):
     torch.cuda.synchronize()
     assert_same(f.get_bits(), F, "filter words (mode %d)" % mode)
     f.close()
+
+
+@pytest.mark.parametrize("qmode", [0, 1, 2])
+def test_query_modes_match_oracle(qmode):
+    w = synth.in_cache_workload(scale=0.01)
+    params = (w["k"], w["s"], w["m"], w["H"], w["bits"])
+    ob, oa = oracle_run(params, [w["insert"]], w["query"])
+    f = Filter(*params)
+    f.set_query_mode(qmode)
+    f.insert(dev(w["insert"][0]), dev(w["insert"][1].view(np.int64)))
+    out = f.query(dev(w["query"][0]), dev(w["query"][1].view(np.int64)))
+    torch.cuda.synchronize()
+    assert_same(out.cpu().numpy(), oa, "answers (query mode %d)" % qmode)
+    f.close()
+
+
+@pytest.mark.parametrize("wgs", [0, 1, 4])
+def test_persistent_launch_shapes_match_oracle(wgs):
+    """Persistent grids taking tiles from the device work queue give the
+    same filter and answers as one workgroup per tile."""
+    w = synth.in_cache_workload(scale=0.01)
+    params = (w["k"], w["s"], w["m"], w["H"], w["bits"])
+    ob, oa = oracle_run(params, [w["insert"]], w["query"])
+    for qmode in (0, 1, 2):
+        f = Filter(*params)
+        f.set_launch(wgs, wgs)
+        f.set_query_mode(qmode)
+        f.insert(dev(w["insert"][0]), dev(w["insert"][1].view(np.int64)))
+        out = f.query(dev(w["query"][0]), dev(w["query"][1].view(np.int64)))
+        torch.cuda.synchronize()
+        assert_same(f.get_bits(), ob, "filter words (wgs %d)" % wgs)
+        assert_same(out.cpu().numpy(), oa, "answers (wgs %d, query mode %d)" % (wgs, qmode))
+        f.close()
+
+
+def test_graph_replays_match_eager_and_oracle():
+    """A captured graph (clear, mark, insert, query) replayed several times,
+    with eager work and synchronisation between replays, gives the oracle's
+    filter and answers every time."""
+    from paper_2606_24417_amd import Graph
+
+    w = synth.in_cache_workload(scale=0.01)
+    params = (w["k"], w["s"], w["m"], w["H"], w["bits"])
+    ob, oa = oracle_run(params, [w["insert"]], w["query"])
+    f = Filter(*params)
+    f.set_launch(2, 2)
+    ins, ioff = dev(w["insert"][0]), dev(w["insert"][1].view(np.int64))
+    q, qoff = dev(w["query"][0]), dev(w["query"][1].view(np.int64))
+    out = torch.zeros(q.numel(), dtype=torch.uint8, device=q.device)
+    g = Graph(f, ins, ioff, q, qoff, out, clear_first=True)
+    for rep in range(3):
+        out.zero_()
+        f.insert(dev(synth.uniform_acgt(5000, rep)))  # eager work that the graph's clear undoes
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert_same(f.get_bits(), ob, "filter words after replay %d" % rep)
+        assert_same(out.cpu().numpy(), oa, "answers after replay %d" % rep)
+    g.close()
+    f.close()
+
+
+def test_autotune_picks_settings_and_keeps_results():
+    w = synth.in_cache_workload(scale=0.01)
+    params = (w["k"], w["s"], w["m"], w["H"], w["bits"])
+    ob, oa = oracle_run(params, [w["insert"]], w["query"])
+    f = Filter(*params)
+    ins, ioff = dev(w["insert"][0]), dev(w["insert"][1].view(np.int64))
+    q, qoff = dev(w["query"][0]), dev(w["query"][1].view(np.int64))
+    report = f.autotune(ins, ioff, q, qoff)
+    print(report)
+    assert "best insert" in report and "best query" in report
+    assert not f.get_bits().any()  # tuning inserts into a scratch filter
+    f.insert(ins, ioff)
+    out = f.query(q, qoff)
+    torch.cuda.synchronize()
+    assert_same(f.get_bits(), ob, "filter words after autotune")
+    assert_same(out.cpu().numpy(), oa, "answers after autotune")
+    f.close()
