@@ -181,12 +181,176 @@ def run_probes(sizes_mib, copy_only=False):
     return out
 
 
+def bench_batched(args):
+    """Batched form: the whole insert batch and query batch in one persistent
+    launch each, captured in a HIP graph, against the plain per-batch launch
+    of the same reads in batches of 2000 reads.  Bits and answers must match."""
+    import torch
+
+    from paper_2606_24417_amd import Filter, Graph
+
+    t0 = time.perf_counter()
+    w = synth.batched_workload(args.scale)
+    ins, ioff = w["insert"]
+    qs, qoff = w["query"]
+    k = w["k"]
+    print("[bench] batched workload in %.1fs: %d+%d reads, %d+%d bases" % (
+        time.perf_counter() - t0, ioff.size - 1, qoff.size - 1, ins.size, qs.size), file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    d_ins = torch.from_numpy(ins).to(dev)
+    d_ioff = torch.from_numpy(ioff.view(np.int64)).to(dev)
+    d_q = torch.from_numpy(qs).to(dev)
+    d_qoff = torch.from_numpy(qoff.view(np.int64)).to(dev)
+    f = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
+    report = f.autotune(d_ins, d_ioff, d_q, d_qoff)
+    print(report, file=sys.stderr, flush=True)
+    tuned = f.get_launch()
+    out_g = torch.zeros(qs.size, dtype=torch.uint8, device=dev)
+    g = Graph(f, d_ins, d_ioff, d_q, d_qoff, out_g, clear_first=True)
+    # plain per-batch launches: batches of 2000 reads, one workgroup per tile
+    per = 2000
+    nb_i = (ioff.size - 1 + per - 1) // per
+    nb_q = (qoff.size - 1 + per - 1) // per
+
+    def batches(off, dseq, nb):
+        res = []
+        for b in range(nb):
+            r0, r1 = b * per, min(off.size - 1, (b + 1) * per)
+            a0, a1 = int(off[r0]), int(off[r1])
+            res.append((dseq[a0:a1], torch.from_numpy((off[r0:r1 + 1] - off[r0]).view(np.int64)).to(dev), a0, a1))
+        return res
+
+    bi = batches(ioff, d_ins, nb_i)
+    bq = batches(qoff, d_q, nb_q)
+    out_p = torch.zeros(qs.size, dtype=torch.uint8, device=dev)
+    h = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
+
+    def plain_step():
+        h.clear()
+        for seq, off, a0, a1 in bi:
+            h.insert(seq, off)
+        for seq, off, a0, a1 in bq:
+            h.query(seq, off, out=out_p[a0:a1])
+
+    def graph_step():
+        g.launch()
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t) * 1e3)
+        return float(np.median(times)), times
+
+    plain_ms, _ = timed(plain_step, max(1, args.steps // 4))
+    graph_ms, gt = timed(graph_step, args.steps)
+    same_bits = bool(np.array_equal(f.get_bits(), h.get_bits()))
+    same_ans = bool(torch.equal(out_g, out_p))
+    n_kmers = kmer_positions(ioff, k) + kmer_positions(qoff, k)
+    res = {"metric": "batched form: insert+query k-mers/s, one persistent launch under hipGraph vs per-batch launches",
+           "value": n_kmers / (graph_ms * 1e-3), "unit": "k-mers/s", "graph_ms": round(graph_ms, 3),
+           "plain_per_batch_ms": round(plain_ms, 3), "speedup": round(plain_ms / graph_ms, 2),
+           "plain_batches": nb_i + nb_q, "reads_per_batch": per, "tuned": tuned,
+           "identical_bits": same_bits, "identical_answers": same_ans,
+           "p50_ms": round(float(np.percentile(gt, 50)), 3), "p99_ms": round(float(np.percentile(gt, 99)), 3),
+           "config": {"workload": w["name"], "filter_bits": f.num_bits, "kmers": n_kmers}}
+    g.close()
+    f.close()
+    h.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_served(args):
+    """Served form: the out-of-cache (or, with --scale, smaller) genome stays
+    resident; query requests of 1..10000 reads (log-uniform count, log-normal
+    lengths) arrive by a Poisson process; report p50/p99 latency and k-mers/s
+    per offered rate, with every answer checked against a direct query."""
+    import torch
+
+    from paper_2606_24417_amd import Filter, Server
+
+    t0 = time.perf_counter()
+    if args.scale >= 1.0:
+        lens = synth.out_of_cache_contigs(301)
+        g = synth.genome(lens, 301)
+    else:
+        g = synth.genome([int(20_000_000 * args.scale * 30)] * 5, 301)
+    kmers = int(np.maximum(np.diff(g[1].astype(np.int64)) - 30, 0).sum())
+    f = Filter(31, 28, 16, 4, 16 * kmers)
+    dev = torch.device("cuda:0")
+    f.insert(torch.from_numpy(g[0]).to(dev), torch.from_numpy(g[1].view(np.int64)).to(dev))
+    torch.cuda.synchronize()
+    print("[bench] served filter: %d bases inserted, %d bits, %.1fs" % (g[0].size, f.num_bits,
+                                                                        time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    rng = np.random.default_rng(501)
+    nreq = args.requests
+    counts = np.exp(rng.uniform(0, np.log(10_000), nreq)).astype(np.int64)
+    reqs = []
+    for i, c in enumerate(counts):
+        L = synth.lognormal_lengths(int(c), 502_000 + i)
+        if i % 2 == 0:
+            seq, off = synth.sample_reads(g[0], g[1], int(c), L, 503_000 + i)
+        else:
+            seq, off = synth.random_reads(int(c), L, 504_000 + i)
+        reqs.append((torch.from_numpy(seq).pin_memory(), off, torch.zeros(seq.size, dtype=torch.uint8).pin_memory()))
+    total_bases = sum(int(r[1][-1]) for r in reqs)
+    req_kmers = [kmer_positions(r[1], 31) for r in reqs]
+    print("[bench] %d requests, %d bases, %.1fs" % (nreq, total_bases, time.perf_counter() - t0), file=sys.stderr,
+          flush=True)
+    # answers of a direct device query, for checking
+    ref = []
+    for seq, off, _ in reqs[: min(nreq, 64)]:
+        ref.append(f.query(seq.to(dev), torch.from_numpy(off.view(np.int64)).to(dev)).cpu())
+    slot_bases = max(1 << 26, max(int(r[1][-1]) for r in reqs))
+    slot_recs = max(1 << 16, max(r[1].size - 1 for r in reqs))
+    rows = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        sv = Server(f, slots=args.slots, slot_bases=slot_bases, slot_records=slot_recs, max_pending=1 << 20)
+        gaps = rng.exponential(1.0 / rate, nreq)
+        tickets = []
+        start = time.perf_counter()
+        due = start
+        for i, (seq, off, out) in enumerate(reqs):
+            due += gaps[i]
+            while time.perf_counter() < due:
+                pass
+            tickets.append(sv.submit(seq, off, out))
+        lat = [sv.wait(t)[0] for t in tickets]
+        span = time.perf_counter() - start
+        st = sv.stats()
+        sv.close()
+        ok = all(torch.equal(reqs[i][2], ref[i]) for i in range(len(ref)))
+        row = {"offered_req_per_s": rate, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3), "kmers_per_s": sum(req_kmers) / span,
+               "achieved_req_per_s": round(nreq / span, 1), "batches": st["batches"],
+               "max_batch_requests": st["max_batch_requests"], "answers_match_direct_query": ok}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    res = {"metric": "served form: query latency p50/p99 (ms) and k-mers/s under Poisson arrivals",
+           "unit": "ms", "higher_is_better": False, "value": rows[0]["p50_ms"], "rates": rows,
+           "config": {"workload": "served: %d bp genome resident, %d requests of 1..10000 reads" % (g[0].size, nreq),
+                      "filter_bits": f.num_bits, "slots": args.slots, "slot_bases": slot_bases}}
+    f.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="in_cache", choices=["in_cache", "out_of_cache", "tiny"])
+    ap.add_argument("--workload", default="in_cache",
+                    choices=["in_cache", "out_of_cache", "tiny", "batched", "served"])
+    ap.add_argument("--scale", type=float, default=1.0, help="batched/served workload size factor")
+    ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000", help="served: offered requests/s")
+    ap.add_argument("--requests", type=int, default=1000, help="served: requests per offered rate")
+    ap.add_argument("--slots", type=int, default=4, help="served: server execution slots")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")
     ap.add_argument("--bits", type=int, default=0, help="filter size override (default: the workload's)")
@@ -209,6 +373,13 @@ def main():
         return
     if args.probe_copy_mib:
         run_probes([args.probe_copy_mib], copy_only=True)
+        return
+
+    if args.workload == "batched":
+        bench_batched(args)
+        return
+    if args.workload == "served":
+        bench_served(args)
         return
 
     import torch

@@ -47,6 +47,7 @@ extern "C" {
 #define SBF_E_INVAL (-1)  /* bad argument: parameters, NULL pointer, size */
 #define SBF_E_NOMEM (-2)  /* a device or host allocation failed */
 #define SBF_E_DEVICE (-3) /* a HIP call or kernel launch failed */
+#define SBF_E_BUSY (-4)   /* a request was not admitted: the server's queue is full */
 
 /* Kernel families (sbf_set_variant). */
 #define SBF_VARIANT_AUTO 0    /* rolling kernel when compiled for (k,s,m,H), else generic */
@@ -219,6 +220,43 @@ void sbf_graph_destroy(sbf_graph *g);
 int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec,
                  const char *d_q, uint64_t q_len, const uint64_t *d_q_off, uint64_t q_nrec, char *report,
                  uint64_t report_len);
+
+/* Served form: a request loop over a resident filter with continuous
+ * batching.  The server runs a scheduler thread with `slots` execution slots
+ * (1..16), each a HIP stream with device staging for slot_bases bases and
+ * slot_records records (the memory budget is slots x (2 x slot_bases +
+ * slot_bases/8 + 8 x slot_records) bytes).  Whenever a slot is free, it
+ * admits the pending requests in arrival order while they fit the slot,
+ * joins them into one record batch, and runs copy-in, record-start marking,
+ * the query kernel and copy-out on the slot's stream; later requests join
+ * the next free slot, so batches overlap on the device.  While a server
+ * exists, use the filter only through it (queries) or after destroying it.
+ *
+ * sbf_server_submit: one query request, a record batch in host memory (seq,
+ * off with nrec+1 entries, off[0] = 0; out receives off[nrec] bytes as in
+ * sbf_query_batch).  The buffers must stay valid and unchanged until the
+ * request completes; pinned host memory lets the copies run asynchronously.
+ * Returns a ticket.  SBF_E_INVAL if the request cannot fit one slot,
+ * SBF_E_BUSY if max_pending requests are already waiting.
+ * sbf_server_poll: 1 when the request is done, 0 while it is not.
+ * sbf_server_wait: block until done, release the ticket, and report the
+ * latency from submission to answers in host memory and the part spent
+ * waiting for admission (either pointer may be NULL); returns the request's
+ * status.
+ * sbf_server_stats: batches run, requests and bases answered, and the most
+ * requests joined in one batch.
+ * sbf_server_destroy: finish every admitted and pending request, then free
+ * the server. */
+typedef struct sbf_server sbf_server;
+sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases, uint64_t slot_records,
+                              uint32_t max_pending);
+int sbf_server_submit(sbf_server *sv, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out,
+                      uint64_t *ticket);
+int sbf_server_poll(sbf_server *sv, uint64_t ticket);
+int sbf_server_wait(sbf_server *sv, uint64_t ticket, double *latency_ms, double *queue_ms);
+int sbf_server_stats(sbf_server *sv, uint64_t *batches, uint64_t *requests, uint64_t *bases,
+                     uint64_t *max_batch_requests);
+void sbf_server_destroy(sbf_server *sv);
 
 /* Bytes of sequence the host entry points stage on the device per chunk
  * (default 256 MiB; at least 4096).  Inputs longer than this are processed in

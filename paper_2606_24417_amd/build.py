@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsbf.so")
-SOURCES = ["sbf_api.hip", "kernels_rolling.hip", "kernels_generic.hip"]
+SOURCES = ["sbf_api.hip", "sbf_server.hip", "kernels_rolling.hip", "kernels_generic.hip"]
 PROBE_LIB = os.path.join(PKG, "libsbf_probe.so")
 PROBE_SOURCES = ["probe_random_access.hip"]
 
@@ -20,6 +20,7 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    "-pthread",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

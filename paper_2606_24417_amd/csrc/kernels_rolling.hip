@@ -211,7 +211,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
     const int g0 = threadIdx.x * GPL;
     uint32_t a[NGW];
     uint64_t vbits = 0, sbits = 0;
-  #pragma unroll
+#pragma unroll
     for (int i = 0; i < NGW; ++i) {
       a[i] = s_codes[g0 + i];
       if (i < 4) {
@@ -227,12 +227,12 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
     // reuses pairs P(j) = oh(j) | oh(j+1): A(r) = P(r) | P(r+2).
     uint64_t oh[L + Z][4];
     uint64_t pr[L + Z][4];
-  #pragma unroll
+#pragma unroll
     for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
     if constexpr (Z == 3) {
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j + 1 < Z; ++j)
-  #pragma unroll
+#pragma unroll
         for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
     }
 
@@ -245,18 +245,18 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
     uint64_t suf[W];
     {
       uint64_t hb[W];
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
       suf[W - 1] = hb[W - 1];
-  #pragma unroll
+#pragma unroll
       for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
     }
 
-  #pragma unroll
+#pragma unroll
     for (int q = 0; q * W < L; ++q) {
       uint64_t hb[W];
       uint64_t pre = ~0ull;
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < W; ++i) {
         const int r = q * W + i;
         if (r < L) {
@@ -272,16 +272,16 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
           smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
           uint64_t A[4];
           if constexpr (Z == 3) {
-  #pragma unroll
+#pragma unroll
             for (int w = 0; w < 4; ++w) {
               pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
               A[w] = pr[r][w] | pr[r + 2][w];
             }
           } else {
-  #pragma unroll
+#pragma unroll
             for (int w = 0; w < 4; ++w) {
               uint64_t x = oh[r][w];
-  #pragma unroll
+#pragma unroll
               for (int j = 1; j <= Z; ++j) x |= oh[r + j][w];
               A[w] = x;
             }
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
           const bool cont = open && v && sh == cur;
           if (open && !cont) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
           const uint64_t keep = cont ? ~0ull : 0ull;
-  #pragma unroll
+#pragma unroll
           for (int w = 0; w < 4; ++w) seg[w] = (seg[w] & keep) | A[w];
           open = v;
           cur = sh;
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
       if ((q + 1) * W < L) {
         hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
         suf[W - 1] = hb[W - 1];
-  #pragma unroll
+#pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
       }
     }
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
       const int t = threadIdx.x;
       uint32_t a[NGW];
       uint64_t vbits = 0, sbits = 0;
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < NGW; ++i) {
         a[i] = s_codes[t + i];
         if (i < 4) {
@@ -371,17 +371,17 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
       uint64_t suf[W];
       {
         uint64_t hb[W];
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
         suf[W - 1] = hb[W - 1];
-  #pragma unroll
+#pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
       }
-  #pragma unroll
+#pragma unroll
       for (int q = 0; q * W < L; ++q) {
         uint64_t hb[W];
         uint64_t pre = ~0ull;
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < W; ++i) {
           const int r = q * W + i;
           if (r < L) {
@@ -399,14 +399,14 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
         if ((q + 1) * W < L) {
           hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
           suf[W - 1] = hb[W - 1];
-  #pragma unroll
+#pragma unroll
           for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
         }
       }
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < L; ++j) s_bits[t * L + j] = pack_bit_addresses<H>(smer_hash(smer_at<S>(a, j)));
       if (t == WG - 1) {
-  #pragma unroll
+#pragma unroll
         for (int j = L; j < L + Z; ++j) s_bits[t * L + j] = pack_bit_addresses<H>(smer_hash(smer_at<S>(a, j)));
       }
     }
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
 
     // ---- phase 2: one k-mer per lane, consecutive k-mers across the wave ----
     const int lane = threadIdx.x & 63;
-  #pragma unroll 2
+#pragma unroll 2
     for (int i = 0; i < L; ++i) {
       const int q = i * WG + threadIdx.x;
       const bool v = (s_kv[q >> 4] >> (q & 15)) & 1u;
@@ -433,10 +433,10 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
           wd[0] = lo.x; wd[1] = lo.y; wd[2] = lo.z; wd[3] = lo.w;
           wd[4] = hi.x; wd[5] = hi.y; wd[6] = hi.z; wd[7] = hi.w;
         } else {
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 8; ++j) wd[j] = 0;
         }
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < 8; ++j) wd[j] = (uint32_t)__builtin_amdgcn_ds_bpermute(leader << 2, (int)wd[j]);
       } else {
         if (v) {
@@ -445,18 +445,18 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
           wd[0] = lo.x; wd[1] = lo.y; wd[2] = lo.z; wd[3] = lo.w;
           wd[4] = hi.x; wd[5] = hi.y; wd[6] = hi.z; wd[7] = hi.w;
         } else {
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 8; ++j) wd[j] = 0;
         }
       }
       uint64_t w4[4];
-  #pragma unroll
+#pragma unroll
       for (int w = 0; w < 4; ++w) w4[w] = ((uint64_t)wd[2 * w + 1] << 32) | wd[2 * w];
       uint32_t acc = 0xFFFFFFFFu;
-  #pragma unroll
+#pragma unroll
       for (int p = 0; p <= Z; ++p) {
         const Pack b = s_bits[q + p];
-  #pragma unroll
+#pragma unroll
         for (int t = 0; t < H; ++t) acc &= (uint32_t)(w4[t & 3] >> ((uint32_t)(b >> (8 * t)) & 63u));
       }
       const uint64_t pos = base + (uint64_t)q;
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
     const int g0 = threadIdx.x * GPL;
     uint32_t a[NGW];
     uint64_t vbits = 0, sbits = 0;
-  #pragma unroll
+#pragma unroll
     for (int i = 0; i < NGW; ++i) {
       a[i] = s_codes[g0 + i];
       if (i < 4) {
@@ -512,7 +512,7 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
     const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
     const uint64_t pos0 = base + (uint64_t)threadIdx.x * L;
     uint32_t res[L / 4];
-  #pragma unroll
+#pragma unroll
     for (int i = 0; i < L / 4; ++i) res[i] = 0;
 
     if (kv != 0) {
@@ -520,26 +520,26 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
       uint64_t pr[L + Z][4];
       uint64_t need[L][4];     // A(r), kept D k-mers
       uint64_t got[L][4];      // shard of k-mer r, kept D k-mers
-  #pragma unroll
+#pragma unroll
       for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
       if constexpr (Z == 3) {
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j + 1 < Z; ++j)
-  #pragma unroll
+#pragma unroll
           for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
       }
       uint64_t suf[W];
       {
         uint64_t hb[W];
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
         suf[W - 1] = hb[W - 1];
-  #pragma unroll
+#pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
       }
       auto test = [&](int r) {
         uint32_t miss = 0;
-  #pragma unroll
+#pragma unroll
         for (int w = 0; w < 4; ++w) {
           const uint64_t m = need[r][w] & ~got[r][w];
           miss |= (uint32_t)m | (uint32_t)(m >> 32);
@@ -547,11 +547,11 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
         const uint32_t present = (miss == 0 && ((kv >> r) & 1ull)) ? 1u : 0u;
         res[r >> 2] |= present << (8 * (r & 3));
       };
-  #pragma unroll
+#pragma unroll
       for (int q = 0; q * W < L; ++q) {
         uint64_t hb[W];
         uint64_t pre = ~0ull;
-  #pragma unroll
+#pragma unroll
         for (int i = 0; i < W; ++i) {
           const int r = q * W + i;
           if (r < L) {
@@ -572,16 +572,16 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
             got[r][3] = ((uint64_t)hi.w << 32) | hi.z;
             smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
             if constexpr (Z == 3) {
-  #pragma unroll
+#pragma unroll
               for (int w = 0; w < 4; ++w) {
                 pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
                 need[r][w] = pr[r][w] | pr[r + 2][w];
               }
             } else {
-  #pragma unroll
+#pragma unroll
               for (int w = 0; w < 4; ++w) {
                 uint64_t x = oh[r][w];
-  #pragma unroll
+#pragma unroll
                 for (int j = 1; j <= Z; ++j) x |= oh[r + j][w];
                 need[r][w] = x;
               }
@@ -592,19 +592,19 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
         if ((q + 1) * W < L) {
           hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
           suf[W - 1] = hb[W - 1];
-  #pragma unroll
+#pragma unroll
           for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
         }
       }
-  #pragma unroll
+#pragma unroll
       for (int r = L - D; r < L; ++r) test(r);
     }
     if (pos0 + L <= n_out) {
       uint4 *o = reinterpret_cast<uint4 *>(out + pos0);
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < L / 16; ++i) o[i] = make_uint4(res[4 * i], res[4 * i + 1], res[4 * i + 2], res[4 * i + 3]);
     } else {
-  #pragma unroll
+#pragma unroll
       for (int r = 0; r < L; ++r)
         if (pos0 + r < n_out) out[pos0 + r] = (uint8_t)(res[r >> 2] >> (8 * (r & 3)));
     }

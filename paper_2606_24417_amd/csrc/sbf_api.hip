@@ -41,6 +41,16 @@ int ok() {
   return SBF_OK;
 }
 
+}  // namespace
+
+int sbf::record_error(int code, const char *msg) {
+  g_err = code;
+  g_msg = msg ? msg : "";
+  return code;
+}
+
+namespace {
+
 int hip_error(hipError_t e, const char *what) {
   if (e == hipErrorOutOfMemory) return set_error(SBF_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
   return set_error(SBF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -629,6 +639,16 @@ void graph_release(sbf_graph *g) {
   delete g;
 }
 
+void appendf(std::string &out, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void appendf(std::string &out, const char *fmt, ...) {
+  char buf[256];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  out += buf;
+}
+
 // fill + mark record starts into s (allocated before any capture)
 int mark_into(Scratch &s, const uint64_t *d_off, uint64_t nrec, uint64_t len, hipStream_t st, const uint32_t **out) {
   *out = nullptr;
@@ -733,11 +753,7 @@ int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint6
     return set_error(SBF_E_INVAL, "autotuning needs an insert batch and a query batch");
   if ((rc = set_device(f))) return rc;
   std::string rep;
-  auto line = [&](const char *fmt, auto... args) {
-    char buf[256];
-    snprintf(buf, sizeof buf, fmt, args...);
-    rep += buf;
-  };
+#define line(...) appendf(rep, __VA_ARGS__)
   if (!use_rolling(f)) {
     line("generic kernels: nothing to tune\n");
   } else {
@@ -832,6 +848,7 @@ int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint6
     line("best query: %s, workgroups/CU %u (%.4f ms)\n",
          bq_mode == SBF_QUERY_LANE ? "lane" : bq_mode == SBF_QUERY_LEADER ? "leader" : "direct", bq_shape, best_q);
   }
+#undef line
   if (report && report_len) {
     const size_t n = std::min<size_t>(rep.size(), report_len - 1);
     memcpy(report, rep.data(), n);

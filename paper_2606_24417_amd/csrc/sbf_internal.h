@@ -54,6 +54,10 @@ hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const 
 hipError_t launch_insert_generic(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st);
 hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);
 
+// Record the calling thread's last error (code and message) for
+// sbf_last_error; returns code.
+int record_error(int code, const char *msg);
+
 // Utility kernels.
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st);

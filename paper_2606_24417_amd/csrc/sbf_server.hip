@@ -1,0 +1,352 @@
+// Served form: a request loop over a resident filter with continuous
+// batching.  A scheduler thread owns `slots` execution slots (a HIP stream, a
+// device staging area for `slot_bases` bases / `slot_records` records, and an
+// event).  Whenever a slot is free it takes pending query requests in arrival
+// order for as long as they fit its memory, concatenates them into one record
+// batch (copies in, record-start marking, query kernel, copies out), and
+// records the slot's event.  Requests that arrive while slots are busy wait
+// in the queue and join the next batch of the first slot that frees up, so
+// the copies and kernels of different batches overlap on the device.  The
+// server uses the filter only through the public stream-ordered entry points.
+#include "sbf.h"
+#include "sbf_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+enum : int { kPending = 1, kRunning = 2, kDone = 0 };
+
+struct Request {
+  uint64_t id = 0;
+  const char *seq = nullptr;
+  const uint64_t *off = nullptr;
+  uint64_t nrec = 0;
+  uint8_t *out = nullptr;
+  uint64_t bases = 0;
+  int64_t t_submit = 0, t_start = 0, t_done = 0;
+  int state = kPending;
+  int status = SBF_OK;
+  std::string error;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  char *d_seq = nullptr;
+  uint8_t *d_out = nullptr;
+  uint64_t *d_off = nullptr;
+  uint32_t *d_starts = nullptr;
+  uint64_t *h_off = nullptr;  // pinned; reused once the slot's event has completed
+  std::vector<Request *> reqs;
+  bool busy = false;
+};
+
+}  // namespace
+
+struct sbf_server {
+  sbf_filter *f = nullptr;
+  int device = 0;
+  uint64_t cap_bases = 0, cap_records = 0;
+  uint32_t max_pending = 0;
+  std::vector<Slot> slots;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request *> pending;
+  std::unordered_map<uint64_t, Request *> live;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread thread;
+  uint64_t batches = 0, requests_done = 0, bases_done = 0, max_batch_requests = 0;
+};
+
+namespace {
+
+int fail(int code, const std::string &msg) { return sbf::record_error(code, msg.c_str()); }
+int succeed() { return sbf::record_error(SBF_OK, ""); }
+
+void release_slot(Slot &s) {
+  if (s.stream) (void)hipStreamSynchronize(s.stream);
+  if (s.d_seq) (void)hipFree(s.d_seq);
+  if (s.d_out) (void)hipFree(s.d_out);
+  if (s.d_off) (void)hipFree(s.d_off);
+  if (s.d_starts) (void)hipFree(s.d_starts);
+  if (s.h_off) (void)hipHostFree(s.h_off);
+  if (s.done) (void)hipEventDestroy(s.done);
+  if (s.stream) (void)hipStreamDestroy(s.stream);
+  s = Slot();
+}
+
+// Issue one batch on a free slot.  Returns an error message or "".
+std::string launch_batch(sbf_server *sv, Slot &s, const std::vector<Request *> &batch) {
+  uint64_t base = 0, rec = 0;
+  hipError_t e = hipSuccess;
+  for (Request *r : batch) {
+    e = hipMemcpyAsync(s.d_seq + base, r->seq, r->bases, hipMemcpyHostToDevice, s.stream);
+    if (e != hipSuccess) return std::string("copy to device: ") + hipGetErrorString(e);
+    for (uint64_t i = 0; i < r->nrec; ++i) s.h_off[rec + i] = base + r->off[i];
+    rec += r->nrec;
+    base += r->bases;
+  }
+  s.h_off[rec] = base;
+  e = hipMemcpyAsync(s.d_off, s.h_off, (rec + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
+  if (e != hipSuccess) return std::string("copy offsets: ") + hipGetErrorString(e);
+  const char *msg = nullptr;
+  if (sbf_mark_record_starts_dev(s.d_off, rec, base, s.d_starts, s.stream) != SBF_OK ||
+      sbf_query_marked_dev(sv->f, s.d_seq, base, s.d_starts, s.d_out, s.stream) != SBF_OK) {
+    sbf_last_error(&msg);
+    return std::string("query: ") + (msg ? msg : "");
+  }
+  uint64_t at = 0;
+  for (Request *r : batch) {
+    e = hipMemcpyAsync(r->out, s.d_out + at, r->bases, hipMemcpyDeviceToHost, s.stream);
+    if (e != hipSuccess) return std::string("copy to host: ") + hipGetErrorString(e);
+    at += r->bases;
+  }
+  e = hipEventRecord(s.done, s.stream);
+  if (e != hipSuccess) return std::string("event: ") + hipGetErrorString(e);
+  return "";
+}
+
+void finish(sbf_server *sv, std::vector<Request *> &reqs, int status, const std::string &err) {
+  const int64_t t = now_ns();
+  std::lock_guard<std::mutex> lk(sv->mu);
+  for (Request *r : reqs) {
+    r->t_done = t;
+    r->state = kDone;
+    r->status = status;
+    r->error = err;
+    if (status == SBF_OK) {
+      sv->requests_done++;
+      sv->bases_done += r->bases;
+    }
+  }
+  reqs.clear();
+  sv->cv_done.notify_all();
+}
+
+void scheduler(sbf_server *sv) {
+  (void)hipSetDevice(sv->device);
+  for (;;) {
+    bool progress = false;
+    bool any_busy = false;
+    for (Slot &s : sv->slots) {
+      if (!s.busy) continue;
+      const hipError_t q = hipEventQuery(s.done);
+      if (q == hipErrorNotReady) {
+        any_busy = true;
+        continue;
+      }
+      finish(sv, s.reqs, q == hipSuccess ? SBF_OK : SBF_E_DEVICE,
+             q == hipSuccess ? "" : std::string("batch: ") + hipGetErrorString(q));
+      s.busy = false;
+      progress = true;
+    }
+    for (Slot &s : sv->slots) {
+      if (s.busy) continue;
+      std::vector<Request *> batch;
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        uint64_t bases = 0, recs = 0;
+        while (!sv->pending.empty()) {
+          Request *r = sv->pending.front();
+          if (bases + r->bases > sv->cap_bases || recs + r->nrec > sv->cap_records) break;
+          sv->pending.pop_front();
+          bases += r->bases;
+          recs += r->nrec;
+          r->state = kRunning;
+          batch.push_back(r);
+        }
+      }
+      if (batch.empty()) continue;
+      const int64_t t = now_ns();
+      for (Request *r : batch) r->t_start = t;
+      const std::string err = launch_batch(sv, s, batch);
+      if (!err.empty()) {
+        (void)hipStreamSynchronize(s.stream);
+        finish(sv, batch, SBF_E_DEVICE, err);
+        continue;
+      }
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->batches++;
+        if (batch.size() > sv->max_batch_requests) sv->max_batch_requests = batch.size();
+      }
+      s.reqs = std::move(batch);
+      s.busy = true;
+      any_busy = true;
+      progress = true;
+    }
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (!any_busy && sv->pending.empty()) {
+      if (sv->stop) break;
+      sv->cv_work.wait(lk, [sv] { return sv->stop || !sv->pending.empty(); });
+    } else if (!progress) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases, uint64_t slot_records,
+                              uint32_t max_pending) {
+  if (!f || slots < 1 || slots > 16 || slot_bases < 1024 || slot_records < 1 || max_pending < 1) {
+    fail(SBF_E_INVAL, "server needs a filter, 1..16 slots, >= 1024 bases and >= 1 record per slot");
+    return nullptr;
+  }
+  sbf_server *sv = new (std::nothrow) sbf_server;
+  if (!sv) {
+    fail(SBF_E_NOMEM, "host allocation of the server");
+    return nullptr;
+  }
+  sv->f = f;
+  sv->cap_bases = slot_bases;
+  sv->cap_records = slot_records;
+  sv->max_pending = max_pending;
+  hipError_t e = hipGetDevice(&sv->device);
+  sv->slots.resize(slots);
+  for (uint32_t i = 0; i < slots && e == hipSuccess; ++i) {
+    Slot &s = sv->slots[i];
+    e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc((void **)&s.d_seq, slot_bases);
+    if (e == hipSuccess) e = hipMalloc((void **)&s.d_out, slot_bases);
+    if (e == hipSuccess) e = hipMalloc((void **)&s.d_off, (slot_records + 1) * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&s.d_starts, (slot_bases + 31) / 32 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_off, (slot_records + 1) * sizeof(uint64_t), 0);
+  }
+  if (e != hipSuccess) {
+    fail(e == hipErrorOutOfMemory ? SBF_E_NOMEM : SBF_E_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
+    for (Slot &s : sv->slots) release_slot(s);
+    delete sv;
+    return nullptr;
+  }
+  try {
+    sv->thread = std::thread(scheduler, sv);
+  } catch (...) {
+    fail(SBF_E_NOMEM, "scheduler thread");
+    for (Slot &s : sv->slots) release_slot(s);
+    delete sv;
+    return nullptr;
+  }
+  succeed();
+  return sv;
+}
+
+int sbf_server_submit(sbf_server *sv, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out,
+                      uint64_t *ticket) {
+  if (!sv || !off || !ticket || nrec == 0) return fail(SBF_E_INVAL, "server, offsets, ticket and records needed");
+  if (off[0] != 0) return fail(SBF_E_INVAL, "off[0] must be 0");
+  for (uint64_t r = 0; r < nrec; ++r)
+    if (off[r + 1] < off[r]) return fail(SBF_E_INVAL, "offsets decrease");
+  const uint64_t bases = off[nrec];
+  if (bases && (!seq || !out)) return fail(SBF_E_INVAL, "sequence or output is NULL");
+  if (bases > sv->cap_bases || nrec > sv->cap_records)
+    return fail(SBF_E_INVAL, "request of " + std::to_string(bases) + " bases / " + std::to_string(nrec) +
+                                 " records exceeds a slot (" + std::to_string(sv->cap_bases) + " / " +
+                                 std::to_string(sv->cap_records) + ")");
+  Request *r = new (std::nothrow) Request;
+  if (!r) return fail(SBF_E_NOMEM, "host allocation of a request");
+  r->seq = seq;
+  r->off = off;
+  r->nrec = nrec;
+  r->out = out;
+  r->bases = bases;
+  r->t_submit = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) {
+      delete r;
+      return fail(SBF_E_INVAL, "server is stopping");
+    }
+    if (sv->pending.size() >= sv->max_pending) {
+      delete r;
+      return fail(SBF_E_BUSY, "pending queue is full");
+    }
+    r->id = sv->next_id++;
+    sv->live[r->id] = r;
+    if (bases == 0) {
+      r->t_start = r->t_done = r->t_submit;
+      r->state = kDone;
+    } else {
+      sv->pending.push_back(r);
+    }
+    *ticket = r->id;
+  }
+  sv->cv_work.notify_one();
+  return succeed();
+}
+
+int sbf_server_poll(sbf_server *sv, uint64_t ticket) {
+  if (!sv) return fail(SBF_E_INVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->live.find(ticket);
+  if (it == sv->live.end()) return fail(SBF_E_INVAL, "unknown ticket");
+  return it->second->state == kDone ? 1 : 0;
+}
+
+int sbf_server_wait(sbf_server *sv, uint64_t ticket, double *latency_ms, double *queue_ms) {
+  if (!sv) return fail(SBF_E_INVAL, "server is NULL");
+  Request *r;
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->live.find(ticket);
+    if (it == sv->live.end()) return fail(SBF_E_INVAL, "unknown ticket");
+    r = it->second;
+    sv->cv_done.wait(lk, [r] { return r->state == kDone; });
+    sv->live.erase(it);
+  }
+  if (latency_ms) *latency_ms = (r->t_done - r->t_submit) * 1e-6;
+  if (queue_ms) *queue_ms = (r->t_start - r->t_submit) * 1e-6;
+  const int status = r->status;
+  const std::string err = r->error;
+  delete r;
+  if (status != SBF_OK) return fail(status, err);
+  return succeed();
+}
+
+int sbf_server_stats(sbf_server *sv, uint64_t *batches, uint64_t *requests, uint64_t *bases,
+                     uint64_t *max_batch_requests) {
+  if (!sv) return fail(SBF_E_INVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (batches) *batches = sv->batches;
+  if (requests) *requests = sv->requests_done;
+  if (bases) *bases = sv->bases_done;
+  if (max_batch_requests) *max_batch_requests = sv->max_batch_requests;
+  return succeed();
+}
+
+void sbf_server_destroy(sbf_server *sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  if (sv->thread.joinable()) sv->thread.join();
+  for (Slot &s : sv->slots) release_slot(s);
+  for (auto &kv : sv->live) delete kv.second;
+  delete sv;
+}
+
+}  // extern "C"

@@ -20,6 +20,7 @@ SBF_OK = 0
 SBF_E_INVAL = -1
 SBF_E_NOMEM = -2
 SBF_E_DEVICE = -3
+SBF_E_BUSY = -4
 VARIANT_AUTO = 0
 VARIANT_ROLLING = 1
 VARIANT_GENERIC = 2
@@ -67,6 +68,12 @@ SIGNATURES = {
     "sbf_graph_launch": (_int, [_vp, _vp]),
     "sbf_graph_destroy": (None, [_vp]),
     "sbf_autotune": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64]),
+    "sbf_server_create": (_vp, [_vp, _u32, _u64, _u64, _u32]),
+    "sbf_server_submit": (_int, [_vp, _vp, _vp, _u64, _vp, _vp]),
+    "sbf_server_poll": (_int, [_vp, _u64]),
+    "sbf_server_wait": (_int, [_vp, _u64, _vp, _vp]),
+    "sbf_server_stats": (_int, [_vp, _vp, _vp, _vp, _vp]),
+    "sbf_server_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -336,6 +343,70 @@ class Graph:
         if getattr(self, "_h", None):
             lib().sbf_graph_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching query server over a resident filter
+    (sbf_server_create).  Requests are host record batches; pinned buffers
+    (torch ``pin_memory=True``) let the copies run asynchronously."""
+
+    def __init__(self, f: Filter, slots=4, slot_bases=1 << 24, slot_records=1 << 16, max_pending=1 << 16):
+        h = lib().sbf_server_create(f.handle, int(slots), int(slot_bases), int(slot_records), int(max_pending))
+        if not h:
+            code, msg = last_error()
+            raise SBFError(code, msg)
+        self._h = ctypes.c_void_p(h)
+        self._f = f
+        self._keep = {}
+
+    @staticmethod
+    def _ptr(x):
+        if x is None:
+            return None
+        if hasattr(x, "data_ptr"):
+            return ctypes.c_void_p(x.data_ptr())
+        return x.ctypes.data_as(ctypes.c_void_p)
+
+    def submit(self, seq, offsets, out) -> int:
+        """Queue a query of a host record batch; out receives len(seq) bytes.
+        The three buffers stay referenced until wait()."""
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        t = ctypes.c_uint64()
+        _check(lib().sbf_server_submit(self._h, self._ptr(seq), off.ctypes.data_as(ctypes.c_void_p), off.size - 1,
+                                       self._ptr(out), ctypes.byref(t)))
+        self._keep[t.value] = (seq, off, out)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        rc = lib().sbf_server_poll(self._h, int(ticket))
+        if rc < 0:
+            _check(rc)
+        return rc == 1
+
+    def wait(self, ticket: int):
+        """Block until the request is done; returns (latency_ms, queue_ms)."""
+        lat, que = ctypes.c_double(), ctypes.c_double()
+        rc = lib().sbf_server_wait(self._h, int(ticket), ctypes.byref(lat), ctypes.byref(que))
+        self._keep.pop(int(ticket), None)
+        _check(rc)
+        return lat.value, que.value
+
+    def stats(self) -> dict:
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(lib().sbf_server_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["batches", "requests", "bases", "max_batch_requests"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sbf_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -253,3 +253,19 @@ def out_of_cache_workload(scale: float = 1.0):
     q = concat(pos, neg, lpos, lneg)
     return dict(name="out-of-cache: 3 Gbp genome, 10M x 150 bp + 100k long reads", k=31, s=28,
                 m=16, H=4, bits=16 * total, insert=g, query=q)
+
+
+def batched_workload(scale: float = 1.0):
+    """2M reads of log-normal length (median 500 bp, 100..50000) sampled with
+    1% substitutions from a 100 Mbp genome, inserted; then 2M more reads of the
+    same length law, half positive and half random, queried."""
+    n = int(2_000_000 * scale)
+    g = genome([int(20_000_000 * max(scale, 0.05))] * 5, 201)
+    ins = sample_reads(g[0], g[1], n, lognormal_lengths(n, 401), 402)
+    half = n // 2
+    qpos = sample_reads(g[0], g[1], half, lognormal_lengths(half, 403), 404)
+    qneg = random_reads(n - half, lognormal_lengths(n - half, 405), 406)
+    q = concat(qpos, qneg)
+    kmers = int(np.maximum(np.diff(ins[1].astype(np.int64)) - 30, 0).sum())
+    return dict(name="batched: 2M log-normal reads (median 500 bp) inserted, 2M queried", k=31, s=28, m=16, H=4,
+                bits=16 * kmers, insert=ins, query=q)

@@ -70,6 +70,20 @@ def test_null_filter_calls_fail_cleanly(L):
         assert sbf.last_error()[0] == sbf.SBF_E_INVAL
 
 
+def test_server_rejects_bad_arguments_without_a_device(L):
+    from paper_2606_24417_amd import sbf
+
+    assert L.sbf_server_create(None, 1, 1 << 20, 16, 16) is None
+    assert sbf.last_error()[0] == sbf.SBF_E_INVAL
+    t = ctypes.c_uint64()
+    assert L.sbf_server_submit(None, None, None, 0, None, ctypes.byref(t)) == sbf.SBF_E_INVAL
+    assert L.sbf_server_poll(None, 1) == sbf.SBF_E_INVAL
+    assert L.sbf_server_wait(None, 1, None, None) == sbf.SBF_E_INVAL
+    L.sbf_server_destroy(None)
+    assert L.sbf_graph_launch(None, None) == sbf.SBF_E_INVAL
+    L.sbf_graph_destroy(None)
+
+
 def test_probe_library_exports_its_header():
     from paper_2606_24417_amd import build
 
