@@ -340,13 +340,92 @@ def bench_served(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_host(args):
+    """Host-resident input: the in-cache workload's insert and query batches
+    given to the host entry points (chunked, pipelined over two streams),
+    with the caller's buffers pinned or pageable, against the same step on
+    device-resident input.  Wall clock per step; answers and bits must match."""
+    import torch
+
+    from paper_2606_24417_amd import Filter
+
+    w = workload("in_cache" if args.scale >= 1.0 else "tiny")
+    k = w["k"]
+    ins, ioff = w["insert"]
+    qs, qoff = w["query"]
+    n_kmers = kmer_positions(ioff, k) + kmer_positions(qoff, k)
+    dev = torch.device("cuda:0")
+    f = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
+    if args.staging_mib:
+        f.set_staging_bytes(args.staging_mib << 20)
+    d_ins = torch.from_numpy(ins).to(dev)
+    d_ioff = torch.from_numpy(ioff.view(np.int64)).to(dev)
+    d_q = torch.from_numpy(qs).to(dev)
+    d_qoff = torch.from_numpy(qoff.view(np.int64)).to(dev)
+    d_out = torch.empty(qs.size, dtype=torch.uint8, device=dev)
+    p_ins = torch.from_numpy(ins).pin_memory()
+    p_q = torch.from_numpy(qs).pin_memory()
+    p_out = torch.zeros(qs.size, dtype=torch.uint8).pin_memory()
+    h_out = np.zeros(qs.size, dtype=np.uint8)
+
+    def device_step():
+        f.clear(torch.cuda.current_stream())
+        f.insert(d_ins, d_ioff)
+        f.query(d_q, d_qoff, out=d_out)
+        torch.cuda.synchronize()
+
+    def pinned_step():
+        f.clear()
+        f.insert(p_ins, ioff)
+        f.query(p_q, qoff, out=p_out)
+
+    def pageable_step():
+        f.clear()
+        f.insert(ins, ioff)
+        f.query(qs, qoff, out=h_out)
+
+    def timed(fn):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            fn()
+            t.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(t))
+
+    dev_ms = timed(device_step)
+    ref_bits = f.get_bits()
+    ref_ans = d_out.cpu().numpy()
+    pin_ms = timed(pinned_step)
+    same_pin = bool(np.array_equal(f.get_bits(), ref_bits)) and bool(np.array_equal(p_out.numpy(), ref_ans))
+    page_ms = timed(pageable_step)
+    same_page = bool(np.array_equal(f.get_bits(), ref_bits)) and bool(np.array_equal(h_out, ref_ans))
+    pcie_bytes = ins.size + 2 * qs.size  # sequence in, answers back
+    res = {"metric": "host-resident input: insert+query k-mers/s through the host entry points",
+           "value": n_kmers / (pin_ms * 1e-3), "unit": "k-mers/s", "higher_is_better": True,
+           "pinned_ms": round(pin_ms, 3), "pageable_ms": round(page_ms, 3), "device_resident_ms": round(dev_ms, 3),
+           "pageable_kmers_per_s": n_kmers / (page_ms * 1e-3),
+           "device_resident_kmers_per_s": n_kmers / (dev_ms * 1e-3),
+           "transfer_loss_pinned": round(1 - dev_ms / pin_ms, 4),
+           "transfer_loss_pageable": round(1 - dev_ms / page_ms, 4),
+           "host_link_GBps_pinned": round(pcie_bytes / (pin_ms * 1e-3) / 1e9, 2),
+           "identical_to_device_path": same_pin and same_page,
+           "staging_bytes": (args.staging_mib << 20) if args.staging_mib else 64 << 20,
+           "config": {"workload": w["name"], "filter_bits": f.num_bits, "kmers": n_kmers, "bases_in": int(ins.size + qs.size)}}
+    f.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="in_cache",
-                    choices=["in_cache", "out_of_cache", "tiny", "batched", "served"])
+                    choices=["in_cache", "out_of_cache", "tiny", "batched", "served", "host"])
+    ap.add_argument("--staging-mib", type=int, default=0, help="host: chunk size of the host entry points")
     ap.add_argument("--scale", type=float, default=1.0, help="batched/served workload size factor")
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000", help="served: offered requests/s")
     ap.add_argument("--requests", type=int, default=1000, help="served: requests per offered rate")
@@ -380,6 +459,9 @@ def main():
         return
     if args.workload == "served":
         bench_served(args)
+        return
+    if args.workload == "host":
+        bench_host(args)
         return
 
     import torch

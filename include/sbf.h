@@ -130,8 +130,11 @@ int sbf_query_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_
 /* Device form: d_seq holds len = off[nrec] bases, d_off is a device array of
  * nrec+1 offsets (not read by the host, so it is not validated: off[0] must
  * be 0 and off[nrec] must equal len).  Stream-ordered.  The library keeps one
- * scratch buffer of len/8 bytes per stream used (record starts as bits);
- * calls on different streams may overlap. */
+ * scratch buffer of len/8 bytes per stream used (record starts as bits).
+ * Queries on different streams may overlap one another; inserts into one
+ * filter must not overlap another insert under SBF_INSERT_TWO_PASS (a plain
+ * store of one could undo a bit the other has already repaired): order them
+ * on one stream or with events, or use SBF_INSERT_ATOMIC. */
 int sbf_insert_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
                          uint64_t nrec, void *stream);
 int sbf_query_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
@@ -258,9 +261,14 @@ int sbf_server_stats(sbf_server *sv, uint64_t *batches, uint64_t *requests, uint
                      uint64_t *max_batch_requests);
 void sbf_server_destroy(sbf_server *sv);
 
-/* Bytes of sequence the host entry points stage on the device per chunk
- * (default 256 MiB; at least 4096).  Inputs longer than this are processed in
- * chunks that overlap by k-1 bases. */
+/* Bytes of sequence per chunk of the host entry points (default 64 MiB; at
+ * least 4096).  Inputs longer than this are processed in chunks that overlap
+ * by k-1 bases, pipelined over two HIP streams: while one chunk's kernel runs,
+ * the next chunk is copied into pinned host memory and sent to the device,
+ * and the previous chunk's answers come back.  A caller buffer that is
+ * already pinned (hipHostMalloc, torch pin_memory) is copied from or to
+ * directly.  The library holds up to two chunks of device and pinned host
+ * memory (twice that for queries) until the filter is destroyed. */
 int sbf_set_staging_bytes(sbf_filter *f, uint64_t bytes);
 
 #ifdef __cplusplus

@@ -63,12 +63,34 @@ int hip_error(hipError_t e, const char *what) {
   } while (0)
 
 constexpr uint64_t kMaxBits = 1ull << 40;
-constexpr uint64_t kDefaultStaging = 256ull << 20;
+constexpr uint64_t kDefaultStaging = 64ull << 20;
 
 struct Scratch {
   void *ptr = nullptr;
   size_t bytes = 0;
 };
+
+// Pinned host memory (hipHostMalloc), so that copies from and to it run
+// asynchronously with the kernels.
+struct Pinned {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// One stage of the host pipeline: a stream with the device and pinned host
+// buffers of one chunk.  Two stages alternate, so that the host-side copy and
+// the transfers of one chunk overlap the kernel of the other.
+struct PipeSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t kernel_done = nullptr;  // the stage's last kernel has finished
+  hipEvent_t done = nullptr;         // the stage's last chunk has finished, answers included
+  Scratch d_seq, d_out, d_off;
+  Pinned h_seq, h_out, h_off;
+  uint8_t *flush_dst = nullptr;  // caller buffer for the answers waiting in h_out
+  uint64_t flush_len = 0;
+  bool pending = false;
+};
+constexpr int kPipeSlots = 2;
 
 }  // namespace
 
@@ -84,8 +106,8 @@ struct sbf_filter {
   uint32_t query_wgs_per_cu = 0;
   int num_cus = 1;
   uint64_t staging = kDefaultStaging;
-  // host entry points: device staging
-  Scratch stage_seq, stage_out, stage_off;
+  // host entry points: chunk pipeline (created on first use)
+  PipeSlot pipe[kPipeSlots];
   // record-start bits, one buffer per stream
   std::mutex mu;
   std::unordered_map<hipStream_t, Scratch> starts;
@@ -223,56 +245,158 @@ int set_device(const sbf_filter *f) {
   return SBF_OK;
 }
 
-// Host-sequence insert or query of one record batch, staged in chunks.
-// Chunk boundaries fall on k-mer starts; a chunk carries k-1 extra bases.
-int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out, bool query) {
+int grow_pinned(Pinned &p, size_t bytes, const char *what) {
+  if (p.bytes >= bytes) return SBF_OK;
+  if (p.ptr) {
+    hipError_t e = hipHostFree(p.ptr);
+    p.ptr = nullptr;
+    p.bytes = 0;
+    if (e != hipSuccess) return hip_error(e, what);
+  }
+  size_t want = std::max<size_t>(bytes, 4096);
+  hipError_t e = hipHostMalloc(&p.ptr, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    p.ptr = nullptr;
+    return hip_error(e, what);
+  }
+  p.bytes = want;
+  return SBF_OK;
+}
+
+// True when p lies in page-locked host memory the device can copy from
+// asynchronously (hipHostMalloc, torch pin_memory).
+bool host_pinned(const void *p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory: clear the recorded error
+    return false;
+  }
+  return at.type == hipMemoryTypeHost;
+}
+
+int ensure_pipe(sbf_filter *f) {
+  for (PipeSlot &ps : f->pipe) {
+    hipError_t e = hipSuccess;
+    if (!ps.stream) e = hipStreamCreateWithFlags(&ps.stream, hipStreamNonBlocking);
+    if (e == hipSuccess && !ps.kernel_done) e = hipEventCreateWithFlags(&ps.kernel_done, hipEventDisableTiming);
+    if (e == hipSuccess && !ps.done) e = hipEventCreateWithFlags(&ps.done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_error(e, "host pipeline set-up");
+  }
+  return SBF_OK;
+}
+
+// Wait for a stage's last chunk and move its answers to the caller's buffer.
+int finish_slot(PipeSlot &ps) {
+  if (!ps.pending) return SBF_OK;
+  ps.pending = false;
+  SBF_HIP(hipEventSynchronize(ps.done), "kernel execution");
+  if (ps.flush_dst && ps.flush_len) memcpy(ps.flush_dst, ps.h_out.ptr, ps.flush_len);
+  ps.flush_dst = nullptr;
+  ps.flush_len = 0;
+  return SBF_OK;
+}
+
+// After a failure: let the queued work end so that no copy still reads or
+// writes the caller's buffers, and keep the first error.
+int drain_pipe(sbf_filter *f, int rc) {
+  for (PipeSlot &ps : f->pipe) {
+    if (ps.stream) (void)hipStreamSynchronize(ps.stream);
+    ps.pending = false;
+    ps.flush_dst = nullptr;
+  }
+  (void)hipGetLastError();
+  return rc;
+}
+
+// Host-sequence insert or query of one record batch, in chunks of at most
+// `staging` bases whose k-mer starts partition [0, total); a chunk carries
+// k-1 extra bases.  Chunk c runs on pipeline stage c mod 2: the caller's bases
+// are copied into pinned memory (or sent directly when the caller's buffer is
+// pinned), sent to the device, marked, and inserted or queried; answers come
+// back the same way.  The kernels of successive chunks are ordered by events,
+// so inserts never overlap one another.  Queries write answers for k-mer
+// starts [0, n_out).
+int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out, uint64_t n_out,
+               bool query) {
   // earlier stream-ordered work on any stream may still use the filter
   SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
+  int rc;
+  if ((rc = ensure_pipe(f))) return rc;
   const uint64_t k = f->g.k;
   const uint64_t total = off[nrec];
   const uint64_t budget = std::max<uint64_t>(f->staging, 4096);
-  const uint64_t span = budget > k ? budget - (k - 1) : 1;  // k-mer starts per chunk
-  hipStream_t st = f->stream;
-  int rc;
-  if ((rc = grow(f->stage_seq, budget + 64, "staging buffer"))) return rc;
-  if (query && (rc = grow(f->stage_out, budget + 64, "staging buffer"))) return rc;
+  const uint64_t span = budget - (k - 1);  // k-mer starts per chunk
+  const bool in_direct = host_pinned(seq);
+  const bool out_direct = query && host_pinned(out);
+  hipEvent_t prev_kernel = nullptr;
   uint64_t r0 = 0;  // first record overlapping the chunk
-  for (uint64_t c0 = 0; c0 < total; c0 += span) {
+  int si = 0;
+  for (uint64_t c0 = 0; c0 < total; c0 += span, si = (si + 1) % kPipeSlots) {
+    PipeSlot &ps = f->pipe[si];
+    if ((rc = finish_slot(ps))) return drain_pipe(f, rc);
     const uint64_t c1 = std::min(total, c0 + span);       // k-mer starts [c0, c1)
     const uint64_t e1 = std::min(total, c1 + k - 1);      // bases [c0, e1)
+    const uint64_t o1 = std::min(c1, n_out);              // answers wanted for starts [c0, o1)
     while (r0 + 1 < nrec && off[r0 + 1] <= c0) ++r0;
-    // record starts inside (c0, e1) relative to c0
-    uint64_t r1 = r0;
+    uint64_t r1 = r0;  // last record overlapping the chunk
     while (r1 + 1 < nrec && off[r1 + 1] < e1) ++r1;
-    const uint64_t nloc = r1 - r0 + 1;  // records overlapping the chunk
+    const uint64_t nloc = r1 - r0 + 1;
     const uint64_t len = e1 - c0;
-    SBF_HIP(hipMemcpyAsync(f->stage_seq.ptr, seq + c0, len, hipMemcpyHostToDevice, st), "copy sequence to device");
+    hipStream_t st = ps.stream;
+    if ((rc = grow(ps.d_seq, budget + 64, "staging buffer"))) return drain_pipe(f, rc);
+    const char *src = seq + c0;
+    if (!in_direct) {
+      if ((rc = grow_pinned(ps.h_seq, budget + 64, "pinned staging buffer"))) return drain_pipe(f, rc);
+      memcpy(ps.h_seq.ptr, src, len);
+      src = (const char *)ps.h_seq.ptr;
+    }
+    hipError_t e = hipMemcpyAsync(ps.d_seq.ptr, src, len, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return drain_pipe(f, hip_error(e, "copy sequence to device"));
     const uint32_t *starts = nullptr;
     if (nloc > 1) {
-      // local offsets: 0, then each record start inside the chunk, then len
-      if ((rc = grow(f->stage_off, (nloc + 1) * 8, "staging buffer"))) return rc;
-      uint64_t *loc = new (std::nothrow) uint64_t[nloc + 1];
-      if (!loc) return set_error(SBF_E_NOMEM, "host offsets");
+      // local offsets: 0, each record start inside the chunk, then len
+      const size_t ob = (nloc + 1) * 8;
+      if ((rc = grow_pinned(ps.h_off, ob, "pinned staging buffer")) || (rc = grow(ps.d_off, ob, "staging buffer")))
+        return drain_pipe(f, rc);
+      uint64_t *loc = (uint64_t *)ps.h_off.ptr;
       loc[0] = 0;
       for (uint64_t r = 1; r < nloc; ++r) loc[r] = off[r0 + r] - c0;
       loc[nloc] = len;
-      hipError_t e = hipMemcpyAsync(f->stage_off.ptr, loc, (nloc + 1) * 8, hipMemcpyHostToDevice, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      delete[] loc;
-      if (e != hipSuccess) return hip_error(e, "copy offsets to device");
-      if ((rc = record_starts(f, (const uint64_t *)f->stage_off.ptr, nloc, len, st, &starts))) return rc;
+      e = hipMemcpyAsync(ps.d_off.ptr, loc, ob, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return drain_pipe(f, hip_error(e, "copy offsets to device"));
     }
-    SeqArgs a{(const uint8_t *)f->stage_seq.ptr, len, starts, nullptr, 0};
+    if (prev_kernel && (e = hipStreamWaitEvent(st, prev_kernel, 0)) != hipSuccess)
+      return drain_pipe(f, hip_error(e, "pipeline ordering"));
+    if (nloc > 1 && (rc = record_starts(f, (const uint64_t *)ps.d_off.ptr, nloc, len, st, &starts)))
+      return drain_pipe(f, rc);
+    SeqArgs a{(const uint8_t *)ps.d_seq.ptr, len, starts, nullptr, 0};
     if (query) {
-      a.out = (uint8_t *)f->stage_out.ptr;
+      if ((rc = grow(ps.d_out, budget + 64, "staging buffer"))) return drain_pipe(f, rc);
+      a.out = (uint8_t *)ps.d_out.ptr;
       a.n_out = c1 - c0;
-      if ((rc = run_query(f, a, st))) return rc;
-      SBF_HIP(hipMemcpyAsync(out + c0, f->stage_out.ptr, c1 - c0, hipMemcpyDeviceToHost, st), "copy answers to host");
+      rc = run_query(f, a, st);
     } else {
-      if ((rc = run_insert(f, a, st))) return rc;
+      rc = run_insert(f, a, st);
     }
-    SBF_HIP(hipStreamSynchronize(st), "kernel execution");
+    if (rc) return drain_pipe(f, rc);
+    if ((e = hipEventRecord(ps.kernel_done, st)) != hipSuccess) return drain_pipe(f, hip_error(e, "event record"));
+    prev_kernel = ps.kernel_done;
+    if (query && o1 > c0) {
+      uint8_t *dst = out + c0;
+      if (!out_direct) {
+        if ((rc = grow_pinned(ps.h_out, budget + 64, "pinned staging buffer"))) return drain_pipe(f, rc);
+        ps.flush_dst = dst;
+        ps.flush_len = o1 - c0;
+        dst = (uint8_t *)ps.h_out.ptr;
+      }
+      e = hipMemcpyAsync(dst, ps.d_out.ptr, o1 - c0, hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return drain_pipe(f, hip_error(e, "copy answers to host"));
+    }
+    if ((e = hipEventRecord(ps.done, st)) != hipSuccess) return drain_pipe(f, hip_error(e, "event record"));
+    ps.pending = true;
   }
+  for (PipeSlot &ps : f->pipe)
+    if ((rc = finish_slot(ps))) return drain_pipe(f, rc);
   return SBF_OK;
 }
 
@@ -344,9 +468,15 @@ void sbf_destroy(sbf_filter *f) {
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   for (auto &kv : f->queues)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
-  if (f->stage_seq.ptr) (void)hipFree(f->stage_seq.ptr);
-  if (f->stage_out.ptr) (void)hipFree(f->stage_out.ptr);
-  if (f->stage_off.ptr) (void)hipFree(f->stage_off.ptr);
+  for (PipeSlot &ps : f->pipe) {
+    for (Scratch *d : {&ps.d_seq, &ps.d_out, &ps.d_off})
+      if (d->ptr) (void)hipFree(d->ptr);
+    for (Pinned *h : {&ps.h_seq, &ps.h_out, &ps.h_off})
+      if (h->ptr) (void)hipHostFree(h->ptr);
+    if (ps.kernel_done) (void)hipEventDestroy(ps.kernel_done);
+    if (ps.done) (void)hipEventDestroy(ps.done);
+    if (ps.stream) (void)hipStreamDestroy(ps.stream);
+  }
   if (f->words) (void)hipFree(f->words);
   if (f->stream) (void)hipStreamDestroy(f->stream);
   delete f;
@@ -484,7 +614,7 @@ int sbf_insert_seq(sbf_filter *f, const char *seq, uint64_t len) {
   if (!seq) return set_error(SBF_E_INVAL, "sequence is NULL");
   if ((rc = set_device(f))) return rc;
   const uint64_t off[2] = {0, len};
-  if ((rc = host_batch(f, seq, off, 1, nullptr, false))) return rc;
+  if ((rc = host_batch(f, seq, off, 1, nullptr, 0, false))) return rc;
   return ok();
 }
 
@@ -494,27 +624,9 @@ int sbf_query_seq(sbf_filter *f, const char *seq, uint64_t len, uint8_t *out) {
   if (len < f->g.k) return ok();
   if (!seq || !out) return set_error(SBF_E_INVAL, "sequence or output is NULL");
   if ((rc = set_device(f))) return rc;
-  // answers for k-mer starts [0, len-k+1): stage with a per-base output and
-  // copy only the valid prefix of each chunk
+  // one record; answers for k-mer starts [0, len-k+1)
   const uint64_t off[2] = {0, len};
-  const uint64_t k = f->g.k;
-  const uint64_t n_out = len - k + 1;
-  const uint64_t budget = std::max<uint64_t>(f->staging, 4096);
-  const uint64_t span = budget > k ? budget - (k - 1) : 1;
-  if ((rc = grow(f->stage_seq, budget + 64, "staging buffer"))) return rc;
-  if ((rc = grow(f->stage_out, budget + 64, "staging buffer"))) return rc;
-  hipStream_t st = f->stream;
-  (void)off;
-  SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
-  for (uint64_t c0 = 0; c0 < n_out; c0 += span) {
-    const uint64_t c1 = std::min(n_out, c0 + span);
-    const uint64_t e1 = c1 + k - 1;
-    SBF_HIP(hipMemcpyAsync(f->stage_seq.ptr, seq + c0, e1 - c0, hipMemcpyHostToDevice, st), "copy sequence to device");
-    SeqArgs a{(const uint8_t *)f->stage_seq.ptr, e1 - c0, nullptr, (uint8_t *)f->stage_out.ptr, c1 - c0};
-    if ((rc = run_query(f, a, st))) return rc;
-    SBF_HIP(hipMemcpyAsync(out + c0, f->stage_out.ptr, c1 - c0, hipMemcpyDeviceToHost, st), "copy answers to host");
-    SBF_HIP(hipStreamSynchronize(st), "kernel execution");
-  }
+  if ((rc = host_batch(f, seq, off, 1, out, len - f->g.k + 1, true))) return rc;
   return ok();
 }
 
@@ -526,7 +638,7 @@ int sbf_insert_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64
   if (off[nrec] == 0) return ok();
   if (!seq) return set_error(SBF_E_INVAL, "sequence is NULL");
   if ((rc = set_device(f))) return rc;
-  if ((rc = host_batch(f, seq, off, nrec, nullptr, false))) return rc;
+  if ((rc = host_batch(f, seq, off, nrec, nullptr, 0, false))) return rc;
   return ok();
 }
 
@@ -538,7 +650,7 @@ int sbf_query_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_
   if (off[nrec] == 0) return ok();
   if (!seq || !out) return set_error(SBF_E_INVAL, "sequence or output is NULL");
   if ((rc = set_device(f))) return rc;
-  if ((rc = host_batch(f, seq, off, nrec, out, true))) return rc;
+  if ((rc = host_batch(f, seq, off, nrec, out, off[nrec], true))) return rc;
   return ok();
 }
 

@@ -303,18 +303,26 @@ class Filter:
                                              ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
                                              ctypes.c_void_p(out.data_ptr()), st))
             return out
+        # host buffers (numpy arrays or CPU tensors; pinned tensors are copied
+        # without an extra staging copy)
         a = _host_u8(seq)
+        n = max(0, a.size - self.k + 1) if offsets is None else a.size
+        res = np.zeros(n, dtype=np.uint8) if out is None else out
+        if hasattr(res, "data_ptr"):
+            if res.numel() < n or not res.is_contiguous():
+                raise ValueError("out must be a contiguous buffer of at least %d bytes" % n)
+            res_p = ctypes.c_void_p(res.data_ptr())
+        else:
+            if res.size < n or not res.flags.c_contiguous:
+                raise ValueError("out must be a contiguous buffer of at least %d bytes" % n)
+            res_p = res.ctypes.data_as(ctypes.c_void_p)
         if offsets is None:
-            n = max(0, a.size - self.k + 1)
-            res = np.zeros(n, dtype=np.uint8) if out is None else out
             if n:
-                _check(L.sbf_query_seq(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size,
-                                       res.ctypes.data_as(ctypes.c_void_p)))
+                _check(L.sbf_query_seq(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size, res_p))
             return res
         off = np.ascontiguousarray(offsets, dtype=np.uint64)
-        res = np.zeros(a.size, dtype=np.uint8) if out is None else out
         _check(L.sbf_query_batch(self._h, a.ctypes.data_as(ctypes.c_void_p), off.ctypes.data_as(ctypes.c_void_p),
-                                 off.size - 1, res.ctypes.data_as(ctypes.c_void_p)))
+                                 off.size - 1, res_p))
         return res
 
 

@@ -186,6 +186,39 @@ def test_host_chunking_with_small_staging():
     check(HOT + (1 << 16,), [(single, None)], (single, None), path="host", staging=5000)
 
 
+@pytest.mark.parametrize("pin_in,pin_out", [(True, True), (True, False), (False, True)])
+def test_host_pipeline_with_pinned_buffers(pin_in, pin_out):
+    """Host entry points over many small chunks, with the caller's buffers in
+    pinned memory (sent directly) or pageable memory (staged), both ways."""
+    rng = np.random.default_rng(16)
+    ins = random_batch(rng, 400, 1500, 0.001)
+    single = noisy(rng, 60_000, 0.001)
+    q = random_batch(rng, 300, 900)
+    params = HOT + (1 << 16,)
+
+    def host(x):
+        t = torch.from_numpy(np.array(x, copy=True))
+        return t.pin_memory() if pin_in else t
+
+    def out_buf(n):
+        t = torch.full((n,), 7, dtype=torch.uint8)
+        return t.pin_memory() if pin_out else t
+
+    print("case host pipeline", pin_in, pin_out, flush=True)
+    f = Filter(*params)
+    f.set_staging_bytes(6000)
+    f.insert(host(ins[0]), ins[1])
+    f.insert(host(single))
+    qa = f.query(host(q[0]), q[1], out=out_buf(q[0].size))
+    sa = f.query(host(single), out=out_buf(single.size - 30))
+    bits = f.get_bits()
+    f.close()
+    F, oa = oracle_run(params, [ins, (single, None)], q)
+    assert_same(bits, F, "filter words")
+    assert_same(qa.numpy(), oa, "batch answers")
+    assert_same(sa.numpy(), oracle.query(oracle.Params(*params), F, single), "single-sequence answers")
+
+
 def test_unaligned_device_pointers():
     rng = np.random.default_rng(7)
     base = noisy(rng, 40_000, 0.001)
