@@ -221,90 +221,119 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
       }
     }
     const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
-    if (kv == 0) continue;
 
-    // one-hot masks of s-mers r .. r+Z, OR-ed: A(r).  For Z = 3 the window OR
-    // reuses pairs P(j) = oh(j) | oh(j+1): A(r) = P(r) | P(r+2).
-    uint64_t oh[L + Z][4];
-    uint64_t pr[L + Z][4];
-#pragma unroll
-    for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
-    if constexpr (Z == 3) {
-#pragma unroll
-      for (int j = 0; j + 1 < Z; ++j)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
-    }
-
-    uint64_t seg[4] = {0, 0, 0, 0};
-    uint32_t cur = 0;
+    uint64_t seg[4] = {0, 0, 0, 0};  // the open segment's masks
+    uint32_t cur = 0;                // and its shard
     bool open = false;
+    // The lane's first finished segment is held back: the previous lane of the
+    // wave absorbs it into its own last segment when both use one shard (the
+    // super-k-mer crossing the lane boundary then costs one update, not two).
+    uint64_t fseg[4] = {0, 0, 0, 0};
+    uint32_t fsh = 0;
+    bool held = false;
     int nbuf = 0;
-
-    // van Herk sliding minimum: suf[i] = min(h[qW+i .. qW+W-1]) of block q
-    uint64_t suf[W];
-    {
-      uint64_t hb[W];
+    if (kv != 0) {
+      // one-hot masks of s-mers r .. r+Z, OR-ed: A(r).  For Z = 3 the window OR
+      // reuses pairs P(j) = oh(j) | oh(j+1): A(r) = P(r) | P(r+2).
+      uint64_t oh[L + Z][4];
+      uint64_t pr[L + Z][4];
 #pragma unroll
-      for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
-      suf[W - 1] = hb[W - 1];
+      for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
+      if constexpr (Z == 3) {
 #pragma unroll
-      for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
-    }
-
+        for (int j = 0; j + 1 < Z; ++j)
 #pragma unroll
-    for (int q = 0; q * W < L; ++q) {
-      uint64_t hb[W];
-      uint64_t pre = ~0ull;
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        const int r = q * W + i;
-        if (r < L) {
-          uint64_t mu;
-          if (i == 0) {
-            mu = suf[0];
-          } else {
-            hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
-            pre = umin64(pre, hb[i - 1]);
-            mu = umin64(suf[i], pre);
-          }
-          // newest s-mer of k-mer r
-          smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
-          uint64_t A[4];
-          if constexpr (Z == 3) {
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-              pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
-              A[w] = pr[r][w] | pr[r + 2][w];
-            }
-          } else {
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-              uint64_t x = oh[r][w];
-#pragma unroll
-              for (int j = 1; j <= Z; ++j) x |= oh[r + j][w];
-              A[w] = x;
-            }
-          }
-          const bool v = (kv >> r) & 1ull;
-          const uint32_t sh = (uint32_t)mu & shard_mask;
-          const bool cont = open && v && sh == cur;
-          if (open && !cont) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
-          const uint64_t keep = cont ? ~0ull : 0ull;
-#pragma unroll
-          for (int w = 0; w < 4; ++w) seg[w] = (seg[w] & keep) | A[w];
-          open = v;
-          cur = sh;
-          if (r % kSubRun == kSubRun - 1 && r + 1 < L) drain_segments<NW, MODE>(s_buf, nbuf, words);
-        }
+          for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
       }
-      if ((q + 1) * W < L) {
-        hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+
+      // van Herk sliding minimum: suf[i] = min(h[qW+i .. qW+W-1]) of block q
+      uint64_t suf[W];
+      {
+        uint64_t hb[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
         suf[W - 1] = hb[W - 1];
 #pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
       }
+
+#pragma unroll
+      for (int q = 0; q * W < L; ++q) {
+        uint64_t hb[W];
+        uint64_t pre = ~0ull;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+          const int r = q * W + i;
+          if (r < L) {
+            uint64_t mu;
+            if (i == 0) {
+              mu = suf[0];
+            } else {
+              hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+              pre = umin64(pre, hb[i - 1]);
+              mu = umin64(suf[i], pre);
+            }
+            // newest s-mer of k-mer r
+            smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
+            uint64_t A[4];
+            if constexpr (Z == 3) {
+#pragma unroll
+              for (int w = 0; w < 4; ++w) {
+                pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
+                A[w] = pr[r][w] | pr[r + 2][w];
+              }
+            } else {
+#pragma unroll
+              for (int w = 0; w < 4; ++w) {
+                uint64_t x = oh[r][w];
+#pragma unroll
+                for (int j = 1; j <= Z; ++j) x |= oh[r + j][w];
+                A[w] = x;
+              }
+            }
+            const bool v = (kv >> r) & 1ull;
+            const uint32_t sh = (uint32_t)mu & shard_mask;
+            const bool cont = open && v && sh == cur;
+            if (open && !cont) {
+              if (held) {
+                push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
+              } else {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) fseg[w] = seg[w];
+                fsh = cur;
+                held = true;
+              }
+            }
+            const uint64_t keep = cont ? ~0ull : 0ull;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) seg[w] = (seg[w] & keep) | A[w];
+            open = v;
+            cur = sh;
+            if (r % kSubRun == kSubRun - 1 && r + 1 < L) drain_segments<NW, MODE>(s_buf, nbuf, words);
+          }
+        }
+        if ((q + 1) * W < L) {
+          hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+          suf[W - 1] = hb[W - 1];
+#pragma unroll
+          for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+        }
+      }
     }
+    // neighbour merge inside the wave (every lane takes part in the shuffles)
+    const int lane = __lane_id();
+    const uint32_t n_sh = __shfl_down(fsh, 1, 64);
+    const bool n_held = __shfl_down((int)held, 1, 64) != 0 && lane < 63;
+    uint64_t n_m[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) n_m[w] = __shfl_down(fseg[w], 1, 64);
+    const bool absorb = open && n_held && n_sh == cur;
+    if (absorb) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) seg[w] |= n_m[w];
+    }
+    const bool absorbed = __shfl_up((int)absorb, 1, 64) != 0 && lane > 0;
+    if (held && !absorbed) push_segment<NW, MODE>(s_buf, nbuf, words, fsh, fseg);
     if (open) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
     drain_segments<NW, MODE>(s_buf, nbuf, words);
   }
@@ -478,7 +507,8 @@ template <int K, int S, int M, int H, int L, int WG, int D>
 __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                         const uint32_t *__restrict__ starts, int aligned16,
                                                         const uint64_t *__restrict__ words, uint32_t shard_mask,
-                                                        uint8_t *__restrict__ out, uint64_t n_out, TileQueue tq) {
+                                                        uint8_t *__restrict__ out, uint64_t n_out,
+                                                        int out_aligned16, TileQueue tq) {
   constexpr int W = K - M + 1;
   constexpr int Z = K - S;
   constexpr int GPL = L / 16;
@@ -599,7 +629,7 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
 #pragma unroll
       for (int r = L - D; r < L; ++r) test(r);
     }
-    if (pos0 + L <= n_out) {
+    if (out_aligned16 && pos0 + L <= n_out) {
       uint4 *o = reinterpret_cast<uint4 *>(out + pos0);
 #pragma unroll
       for (int i = 0; i < L / 16; ++i) o[i] = make_uint4(res[4 * i], res[4 * i + 1], res[4 * i + 2], res[4 * i + 3]);
@@ -673,7 +703,7 @@ hipError_t query_rolling(const uint64_t *words, uint32_t shard_mask, const SeqAr
     const uint64_t tile = (uint64_t)kQueryLaneL * kQueryLaneWG;
     SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, kQueryLaneL, kQueryLaneWG, kQueryLaneD>), kQueryLaneWG,
                      (a.n_out + tile - 1) / tile, 2, a.seq, a.len, a.starts, aligned, words, shard_mask, a.out,
-                     a.n_out);
+                     a.n_out, (int)(((uintptr_t)a.out & 15u) == 0));
     return hipSuccess;
   }
   const uint64_t tile = 16ull * kQueryWG;

@@ -235,6 +235,30 @@ def test_unaligned_device_pointers():
         f.close()
 
 
+@pytest.mark.parametrize("qmode", [0, 1, 2])
+def test_unaligned_output_pointers(qmode):
+    """Answers written through output views at every offset mod 16."""
+    rng = np.random.default_rng(17)
+    ins = noisy(rng, 30_000, 0.001)
+    q = random_batch(rng, 120, 400)
+    params = HOT + (1 << 16,)
+    F, oa = oracle_run(params, [(ins, None)], q)
+    f = Filter(*params)
+    f.set_query_mode(qmode)
+    f.insert(dev(ins))
+    d_q = dev(q[0])
+    d_off = dev(q[1].astype(np.uint64).view(np.int64))
+    print("case unaligned out", qmode, flush=True)
+    for shift in (1, 5, 8, 13):
+        buf = torch.full((q[0].size + 32,), 9, dtype=torch.uint8, device="cuda")
+        f.query(d_q, d_off, out=buf[shift:shift + q[0].size])
+        torch.cuda.synchronize()
+        got = buf.cpu().numpy()
+        assert_same(got[shift:shift + q[0].size], oa, "answers (shift %d)" % shift)
+        assert (got[:shift] == 9).all() and (got[shift + q[0].size:] == 9).all()
+    f.close()
+
+
 def test_nondefault_stream_and_state_roundtrip():
     rng = np.random.default_rng(8)
     a, b = noisy(rng, 30_000), noisy(rng, 30_000)
