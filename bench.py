@@ -128,29 +128,18 @@ def cpu_baseline(w, budget_s: float = 12.0):
                           k_ins / t_ins, k_q / max(t_q, 1e-9))}
 
 
-def segments_per_kmer(p, batch, sample_bases: int = 4_000_000) -> float:
-    """Super-k-mer segments per k-mer position (one shard access each), counted
-    by the oracle on the records covering the first sample_bases bases and on
-    as many from the middle of the batch."""
-    import oracle
-
-    seq, off = batch
-    nrec = off.size - 1
-    segs = kmers = 0
-    for r0 in (0, nrec // 2):
-        r1 = r0
-        while r1 < nrec and int(off[r1] - off[r0]) < sample_bases // 2:
-            r1 += 1
-        r1 = max(r1, r0 + 1)
-        a, b = int(off[r0]), int(off[r1])
-        sub_off = off[r0:r1 + 1] - off[r0]
-        part = seq[a:b]
-        if sub_off.size == 2 and part.size > sample_bases // 2:
-            part = part[: sample_bases // 2]
-            sub_off = np.array([0, part.size], dtype=np.uint64)
-        segs += oracle.count_segments(p, part, sub_off)
-        kmers += kmer_positions(sub_off, p.k)
-    return segs / max(1, kmers)
+def stored_segments(workload_name: str, part: str, kmers: int):
+    """Super-k-mer segments (one shard access each) of a workload's insert or
+    query batch, as counted over every record by tests/golden/segment_counts.py
+    and stored in tests/golden/segment_counts.json; None when absent or taken on
+    a batch of another size."""
+    path = os.path.join(ROOT, "tests", "golden", "segment_counts.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path)).get(workload_name, {}).get(part)
+    if not d or int(d["kmers"]) != int(kmers):
+        return None
+    return int(d["segments"])
 
 
 def run_probes(sizes_mib, copy_only=False):
@@ -418,13 +407,100 @@ def bench_host(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_sweep(args):
+    """(s, m, H) sweep at k = 31 over s in 24..31, m in 12..20, H in 1..8 on the
+    in-cache workload (scaled by --scale): per point, the FPR on the negative
+    reads, a zero-false-negative check on genome k-mers, and insert and query
+    kernel time.  Then the FPR of independent random 31-mers (each its own
+    record) against filter size at (28, 16, 4)."""
+    import torch
+
+    from paper_2606_24417_amd import Filter
+
+    t0 = time.perf_counter()
+    w = synth.in_cache_workload(args.scale)
+    k = w["k"]
+    ins, ioff = w["insert"]
+    qs, qoff = w["query"]
+    npos = w["n_pos_records"]
+    neg0 = int(qoff[npos])
+    neg_kmers = kmer_positions(qoff[npos:] - qoff[npos], k)
+    n_ins_kmers = kmer_positions(ioff, k)
+    n_q_kmers = kmer_positions(qoff, k)
+    dev = torch.device("cuda:0")
+    d_ins = torch.from_numpy(ins).to(dev)
+    d_ioff = torch.from_numpy(ioff.view(np.int64)).to(dev)
+    d_q = torch.from_numpy(qs).to(dev)
+    d_qoff = torch.from_numpy(qoff.view(np.int64)).to(dev)
+    d_out = torch.empty(qs.size, dtype=torch.uint8, device=dev)
+    fn_len = int(min(ioff[1], 1_000_000))
+    d_fn = d_ins[:fn_len]
+    d_fn_out = torch.empty(fn_len - k + 1, dtype=torch.uint8, device=dev)
+    print("[bench] sweep workload in %.1fs: %d + %d k-mers" % (time.perf_counter() - t0, n_ins_kmers, n_q_kmers),
+          file=sys.stderr, flush=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    rows = []
+    grid = [(s_, m_, h_) for s_ in range(24, 32) for m_ in range(12, 21) for h_ in range(1, 9)]
+    if args.sweep_points:
+        grid = grid[: args.sweep_points]
+    for i, (s_, m_, h_) in enumerate(grid):
+        f = Filter(k, s_, m_, h_, w["bits"])
+        if i == 0:  # warm-up of the first point's kernels
+            f.insert(d_ins, d_ioff)
+            f.query(d_q, d_qoff, out=d_out)
+            f.clear(torch.cuda.current_stream())
+        ev[0].record()
+        f.insert(d_ins, d_ioff)
+        ev[1].record()
+        f.query(d_q, d_qoff, out=d_out)
+        ev[2].record()
+        f.query(d_fn, out=d_fn_out)
+        torch.cuda.synchronize()
+        fp = int(d_out[neg0:].sum().item())
+        no_fn = bool(int(d_fn_out.sum().item()) == fn_len - k + 1)
+        rows.append({"s": s_, "m": m_, "H": h_, "fpr": fp / max(1, neg_kmers),
+                     "insert_ms": round(ev[0].elapsed_time(ev[1]), 4), "query_ms": round(ev[1].elapsed_time(ev[2]), 4),
+                     "variant": "rolling" if f.variant == 1 else "generic", "zero_fn": no_fn})
+        f.close()
+        if (i + 1) % 48 == 0:
+            print("[bench] sweep %d/%d points" % (i + 1, len(grid)), file=sys.stderr, flush=True)
+    # FPR of independent random 31-mers against filter size, (28, 16, 4)
+    n_rand = int(10_000_000 * min(1.0, args.scale * 10))
+    rs = synth.uniform_acgt(31 * n_rand, 211)  # uniform bases, as the Bloom closed form assumes
+    ro = np.arange(n_rand + 1, dtype=np.uint64) * np.uint64(31)
+    d_rs = torch.from_numpy(rs).to(dev)
+    d_ro = torch.from_numpy(ro.view(np.int64)).to(dev)
+    d_rout = torch.empty(rs.size, dtype=torch.uint8, device=dev)
+    curve = []
+    for lg in range(22, 37, 2):
+        f = Filter(k, 28, 16, 4, 1 << lg)
+        f.insert(d_ins, d_ioff)
+        f.query(d_rs, d_ro, out=d_rout)
+        torch.cuda.synchronize()
+        curve.append({"bits": 1 << lg, "bits_per_kmer": round((1 << lg) / n_ins_kmers, 3),
+                      "fpr": int(d_rout.sum().item()) / n_rand})
+        f.close()
+    all_ok = all(r["zero_fn"] for r in rows)
+    best = min(rows, key=lambda r: r["fpr"])
+    fastest = min(rows, key=lambda r: r["insert_ms"] + r["query_ms"])
+    res = {"metric": "sweep: FPR and insert/query kernel ms per (s,m,H) at k=31, 16 bits per k-mer",
+           "unit": "fpr", "points": len(rows), "zero_false_negatives_everywhere": all_ok,
+           "best_fpr": best, "fastest": fastest,
+           "at_28_16_4": next((r for r in rows if (r["s"], r["m"], r["H"]) == (28, 16, 4)), None),
+           "rows": rows, "fpr_vs_size": curve, "random_kmers": n_rand,
+           "config": {"workload": w["name"] + " (scale %g)" % args.scale, "filter_bits": w["bits"],
+                      "insert_kmers": n_ins_kmers, "query_kmers": n_q_kmers, "negative_kmers": neg_kmers}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="in_cache",
-                    choices=["in_cache", "out_of_cache", "tiny", "batched", "served", "host"])
+                    choices=["in_cache", "out_of_cache", "tiny", "batched", "served", "host", "sweep"])
+    ap.add_argument("--sweep-points", type=int, default=0, help="sweep: only the first n (s,m,H) points")
     ap.add_argument("--staging-mib", type=int, default=0, help="host: chunk size of the host entry points")
     ap.add_argument("--scale", type=float, default=1.0, help="batched/served workload size factor")
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000", help="served: offered requests/s")
@@ -462,6 +538,9 @@ def main():
         return
     if args.workload == "host":
         bench_host(args)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args)
         return
 
     import torch
@@ -552,17 +631,17 @@ def main():
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT_TOPS, "unit": "TOP/s (int32)",
                 "frac": round(achieved / PEAK_INT_TOPS, 4)}
     else:
-        import oracle
-
-        p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
         seqs = w["query"] if dom == "query" else w["insert"]
-        seg_per_kmer = segments_per_kmer(p, seqs)
-        nseg = seg_per_kmer * dom_kmers
-        per_seg = 32 if dom == "query" else 64
-        nbytes = nseg * per_seg + seqs[0].size * (2 if dom == "query" else 1)
-        achieved = nbytes / (dom_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4)}
+        nseg = stored_segments(args.workload, dom, dom_kmers)
+        if nseg is None:
+            roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+                    "note": "no stored segment count for this workload"}
+        else:
+            per_seg = 32 if dom == "query" else 64
+            nbytes = nseg * per_seg + seqs[0].size * (2 if dom == "query" else 1)
+            achieved = nbytes / (dom_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(achieved / PEAK_HBM_GBS, 4), "segments": nseg}
     traffic = counter_traffic(args.workload, "%s_rolling" % dom, dom_kmers)
     roof["traffic"] = traffic
     roof["kernel"] = "%s_rolling_kernel<31,28,16,4>" % dom

@@ -550,6 +550,7 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
       uint64_t pr[L + Z][4];
       uint64_t need[L][4];     // A(r), kept D k-mers
       uint64_t got[L][4];      // shard of k-mer r, kept D k-mers
+      uint32_t prev_sh = 0;
 #pragma unroll
       for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
       if constexpr (Z == 3) {
@@ -593,13 +594,19 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
               pre = umin64(pre, hb[i - 1]);
               mu = umin64(suf[i], pre);
             }
+            // A lane loads its shard only where the shard changes (about once
+            // per super-k-mer); elsewhere it reads shard 0, one line shared by
+            // every such lane, and keeps the previous k-mer's words.  Straight-
+            // line code keeps the register footprint of the plain load.
             const uint32_t sh = (uint32_t)mu & shard_mask;
-            const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)sh);
+            const bool fresh = r == 0 || sh != prev_sh;
+            prev_sh = sh;
+            const uint4 *p = reinterpret_cast<const uint4 *>(words + (fresh ? 4ull * (uint64_t)sh : 0ull));
             const uint4 lo = p[0], hi = p[1];
-            got[r][0] = ((uint64_t)lo.y << 32) | lo.x;
-            got[r][1] = ((uint64_t)lo.w << 32) | lo.z;
-            got[r][2] = ((uint64_t)hi.y << 32) | hi.x;
-            got[r][3] = ((uint64_t)hi.w << 32) | hi.z;
+            const uint64_t ld[4] = {((uint64_t)lo.y << 32) | lo.x, ((uint64_t)lo.w << 32) | lo.z,
+                                    ((uint64_t)hi.y << 32) | hi.x, ((uint64_t)hi.w << 32) | hi.z};
+#pragma unroll
+            for (int w = 0; w < 4; ++w) got[r][w] = (r == 0 || fresh) ? ld[w] : got[r > 0 ? r - 1 : 0][w];
             smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
             if constexpr (Z == 3) {
 #pragma unroll
@@ -646,7 +653,7 @@ constexpr int kInsertWG = 256;
 constexpr int kQueryWG = 256;
 constexpr int kQueryLaneL = 32;
 constexpr int kQueryLaneWG = 256;
-constexpr int kQueryLaneD = 2;
+constexpr int kQueryLaneD = 1;
 
 // Grid of a launch over ntiles tiles: one workgroup per tile, or a persistent
 // grid that takes tiles from the queue counter `slot` (reset first).
