@@ -142,7 +142,7 @@ def stored_segments(workload_name: str, part: str, kmers: int):
     return int(d["segments"])
 
 
-def run_probes(sizes_mib, copy_only=False):
+def run_probes(sizes_mib, copy_only=False, modes=None):
     """Random shard-access and copy rates from libsbf_probe.so (include/sbf_probe.h)."""
     import ctypes
 
@@ -154,7 +154,8 @@ def run_probes(sizes_mib, copy_only=False):
                    ctypes.POINTER(ctypes.c_double)]
     names = ["read32", "rmw32", "atomic4", "atomic1", "copy"]
     out = []
-    modes = [4] if copy_only else [0, 1, 2, 3, 4]
+    if modes is None:
+        modes = [4] if copy_only else [0, 1, 2, 3, 4]
     for mib in sizes_mib:
         row = {"buffer_mib": mib}
         for mode in modes:
@@ -511,10 +512,13 @@ def main():
     ap.add_argument("--bits", type=int, default=0, help="filter size override (default: the workload's)")
     ap.add_argument("--query-mode", type=int, default=0, help="0 lane-sequential, 1 leader load + broadcast, 2 every lane loads")
     ap.add_argument("--insert-mode", type=int, default=0, help="0 two-pass, 1 atomic")
-    ap.add_argument("--launch", type=str, default="0,0",
-                    help="persistent workgroups per CU for insert,query (0 = one workgroup per tile)")
+    ap.add_argument("--launch", type=str, default="",
+                    help="persistent workgroups per CU for insert,query (0 = one workgroup per tile; "
+                         "default: the library's)")
     ap.add_argument("--autotune", action="store_true", help="run the library autotuner on the workload first")
     ap.add_argument("--probe", action="store_true", help="print random-access and copy roofline probes, then exit")
+    ap.add_argument("--probe-read-mib", type=int, default=0,
+                    help="run only the random 32-byte read probe on a buffer of this many MiB (counter calibration)")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="run only the streaming-copy probe on a buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -528,6 +532,9 @@ def main():
         return
     if args.probe_copy_mib:
         run_probes([args.probe_copy_mib], copy_only=True)
+        return
+    if args.probe_read_mib:
+        run_probes([args.probe_read_mib], modes=[0])
         return
 
     if args.workload == "batched":
@@ -571,8 +578,9 @@ def main():
         f.variant = args.variant
     f.set_query_mode(args.query_mode)
     f.set_insert_mode(args.insert_mode)
-    li, lq = (int(x) for x in args.launch.split(","))
-    f.set_launch(li, lq)
+    if args.launch:
+        li, lq = (int(x) for x in args.launch.split(","))
+        f.set_launch(li, lq)
     tuned = None
     if args.autotune:
         report = f.autotune(d_ins, d_ioff, d_q, d_qoff)
@@ -621,31 +629,49 @@ def main():
     value = total_kmers / (ms_per_step * 1e-3)
     q_rate = n_q_kmers / (np.median(q_ms) * 1e-3)
     i_rate = n_ins_kmers / (np.median(ins_ms) * 1e-3)
-    dom = "query" if np.mean(q_ms) >= np.mean(ins_ms) else "insert"
-    dom_ms = float(np.mean(q_ms if dom == "query" else ins_ms))
-    dom_kmers = n_q_kmers if dom == "query" else n_ins_kmers
+    # Roofline of the largest single kernel launch.  The insert is two launches
+    # of one kernel (store pass, then repair pass) unless it runs in atomic
+    # mode; the query is one launch.
+    settings = f.get_launch()
+    ins_launches = 1 if settings["insert_mode"] == 1 else 2
+    q_kernel = {0: "query_lane_kernel", 1: "query_rolling_kernel (leader)", 2: "query_rolling_kernel (direct)"}[
+        settings["query_mode"]] + "<31,28,16,4>"
     in_cache = args.workload != "out_of_cache"
-    if in_cache:
-        ops = OPS_PER_KMER[dom] * dom_kmers
-        achieved = ops / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT_TOPS, "unit": "TOP/s (int32)",
-                "frac": round(achieved / PEAK_INT_TOPS, 4)}
-    else:
-        seqs = w["query"] if dom == "query" else w["insert"]
-        nseg = stored_segments(args.workload, dom, dom_kmers)
-        if nseg is None:
-            roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
-                    "note": "no stored segment count for this workload"}
+
+    def roofline(part, ms, kmers, launches):
+        if in_cache:
+            ops = OPS_PER_KMER[part] * kmers
+            achieved = ops / (ms * 1e-3) / 1e12
+            r = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT_TOPS, "unit": "TOP/s (int32)",
+                 "frac": round(achieved / PEAK_INT_TOPS, 4), "ops_per_kmer": OPS_PER_KMER[part]}
         else:
-            per_seg = 32 if dom == "query" else 64
-            nbytes = nseg * per_seg + seqs[0].size * (2 if dom == "query" else 1)
-            achieved = nbytes / (dom_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(achieved / PEAK_HBM_GBS, 4), "segments": nseg}
-    traffic = counter_traffic(args.workload, "%s_rolling" % dom, dom_kmers)
-    roof["traffic"] = traffic
-    roof["kernel"] = "%s_rolling_kernel<31,28,16,4>" % dom
-    roof["kernel_ms"] = round(dom_ms, 4)
+            nseg = stored_segments(args.workload, part, kmers)
+            seqs = w[part]
+            if nseg is None:
+                r = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
+                     "note": "no stored segment count for this workload"}
+            else:
+                per_seg = 32 if part == "query" else 64
+                nbytes = nseg * per_seg + seqs[0].size * (2 if part == "query" else 1)
+                achieved = nbytes / (ms * 1e-3) / 1e9
+                r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "segments": nseg}
+        r["traffic"] = counter_traffic(args.workload, part, kmers)
+        r["launches"] = launches
+        r["kernel_ms"] = round(ms, 4)
+        return r
+
+    q_mean = float(np.mean(q_ms))
+    i_mean = float(np.mean(ins_ms))
+    roof_q = roofline("query", q_mean, n_q_kmers, 1)
+    roof_q["kernel"] = q_kernel
+    roof_i = roofline("insert", i_mean, n_ins_kmers, ins_launches)
+    roof_i["kernel"] = "insert_rolling_kernel<31,28,16,4> (%s)" % (
+        "store + repair passes" if ins_launches == 2 else "atomic")
+    if q_mean >= i_mean / ins_launches:
+        roof, roof_other = roof_q, roof_i
+    else:
+        roof, roof_other = roof_i, roof_q
 
     res = {
         "metric": "insert & query k-mers/s at k=31,s=28,m=16,H=4 on 1 MI355X; p50/p99 batch ms",
@@ -670,8 +696,9 @@ def main():
         "insert_ms_median": round(float(np.median(ins_ms)), 4),
         "query_ms_median": round(float(np.median(q_ms)), 4),
         "query_present": n_q_valid,
-        "settings": f.get_launch(),
+        "settings": settings,
         "roofline": roof,
+        "roofline_other": roof_other,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -189,7 +189,8 @@ int sbf_set_query_mode(sbf_filter *f, int mode);
 /* Launch shape of the rolling kernels: 0 workgroups per CU launches one
  * workgroup per tile; n > 0 launches a persistent grid of n workgroups per
  * compute unit that take tiles from a device work-queue counter until the
- * batch is done.  Insert and query are set separately (n <= 32).  The
+ * batch is done.  Insert and query are set separately (n <= 32; default 4
+ * for both, the fastest measured shape).  The
  * counters live per stream, so persistent calls on one stream are ordered;
  * sbf_get_launch reads the settings back (any pointer may be NULL). */
 int sbf_set_launch(sbf_filter *f, uint32_t insert_wgs_per_cu, uint32_t query_wgs_per_cu);
