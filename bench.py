@@ -142,7 +142,7 @@ def stored_segments(workload_name: str, part: str, kmers: int):
     return int(d["segments"])
 
 
-def run_probes(sizes_mib, copy_only=False, modes=None):
+def run_probes(sizes_mib, copy_only=False, modes=None, quiet=False):
     """Random shard-access and copy rates from libsbf_probe.so (include/sbf_probe.h)."""
     import ctypes
 
@@ -167,7 +167,7 @@ def run_probes(sizes_mib, copy_only=False, modes=None):
             row[key] = round(rate.value / 1e9, 2)
             row[names[mode] + "_ms"] = round(ms.value, 4)
         out.append(row)
-        print(json.dumps(row), flush=True)
+        print(json.dumps(row), file=sys.stderr if quiet else sys.stdout, flush=True)
     return out
 
 
@@ -508,6 +508,7 @@ def main():
     ap.add_argument("--requests", type=int, default=1000, help="served: requests per offered rate")
     ap.add_argument("--slots", type=int, default=4, help="served: server execution slots")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true", help="out_of_cache: skip the random-access probe")
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")
     ap.add_argument("--bits", type=int, default=0, help="filter size override (default: the workload's)")
     ap.add_argument("--query-mode", type=int, default=0, help="0 lane-sequential, 1 leader load + broadcast, 2 every lane loads")
@@ -657,9 +658,21 @@ def main():
                 r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "segments": nseg}
         r["traffic"] = counter_traffic(args.workload, part, kmers)
+        if probe is not None and r.get("segments"):
+            # segments (one random 32-byte shard access each) per second against
+            # the probe's random read rate (query) or read-modify-write rate (insert)
+            seg_rate = r["segments"] / (ms * 1e-3)
+            peak = probe["read32_Gops" if part == "query" else "rmw32_Gops"] * 1e9
+            r["random_access"] = {"segments_per_s": seg_rate, "probe_peak_per_s": peak,
+                                  "probe": "read32" if part == "query" else "rmw32", "frac": round(seg_rate / peak, 4)}
         r["launches"] = launches
         r["kernel_ms"] = round(ms, 4)
         return r
+
+    probe = None
+    if not in_cache and not args.no_probe:
+        # random 32-byte sector rates over an 8 GiB buffer, measured now on this GPU
+        probe = {r["buffer_mib"]: r for r in run_probes([8192], modes=[0, 1], quiet=True)}[8192]
 
     q_mean = float(np.mean(q_ms))
     i_mean = float(np.mean(ins_ms))

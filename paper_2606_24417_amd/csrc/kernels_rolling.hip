@@ -569,11 +569,12 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
       }
       auto test = [&](int r) {
+        // one three-input and-not-or per 32-bit half (v_bitop3 on gfx950)
         uint32_t miss = 0;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          const uint64_t m = need[r][w] & ~got[r][w];
-          miss |= (uint32_t)m | (uint32_t)(m >> 32);
+          miss = ((uint32_t)need[r][w] & ~(uint32_t)got[r][w]) | miss;
+          miss = ((uint32_t)(need[r][w] >> 32) & ~(uint32_t)(got[r][w] >> 32)) | miss;
         }
         const uint32_t present = (miss == 0 && ((kv >> r) & 1ull)) ? 1u : 0u;
         res[r >> 2] |= present << (8 * (r & 3));
@@ -601,7 +602,8 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
             const uint32_t sh = (uint32_t)mu & shard_mask;
             const bool fresh = r == 0 || sh != prev_sh;
             prev_sh = sh;
-            const uint4 *p = reinterpret_cast<const uint4 *>(words + (fresh ? 4ull * (uint64_t)sh : 0ull));
+            const uint32_t lsh = fresh ? sh : 0u;
+            const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)lsh);
             const uint4 lo = p[0], hi = p[1];
             const uint64_t ld[4] = {((uint64_t)lo.y << 32) | lo.x, ((uint64_t)lo.w << 32) | lo.z,
                                     ((uint64_t)hi.y << 32) | hi.x, ((uint64_t)hi.w << 32) | hi.z};
