@@ -311,7 +311,8 @@ def bench_served(args):
             while time.perf_counter() < due:
                 pass
             tickets.append(sv.submit(seq, off, out))
-        lat = [sv.wait(t)[0] for t in tickets]
+        waits = [sv.wait(t) for t in tickets]
+        lat = [x[0] for x in waits]
         span = time.perf_counter() - start
         st = sv.stats()
         sv.close()
@@ -319,7 +320,10 @@ def bench_served(args):
         row = {"offered_req_per_s": rate, "p50_ms": round(float(np.percentile(lat, 50)), 3),
                "p99_ms": round(float(np.percentile(lat, 99)), 3), "kmers_per_s": sum(req_kmers) / span,
                "achieved_req_per_s": round(nreq / span, 1), "batches": st["batches"],
-               "max_batch_requests": st["max_batch_requests"], "answers_match_direct_query": ok}
+               "max_batch_requests": st["max_batch_requests"], "answers_match_direct_query": ok,
+               "p99_queue_ms": round(float(np.percentile([x[1] for x in waits], 99)), 3),
+               "slowest": [{"ms": round(lat[i], 3), "queue_ms": round(waits[i][1], 3), "index": int(i),
+                            "bases": int(reqs[i][1][-1])} for i in np.argsort(lat)[::-1][:3]]}
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
     res = {"metric": "served form: query latency p50/p99 (ms) and k-mers/s under Poisson arrivals",
@@ -446,21 +450,23 @@ def bench_sweep(args):
         grid = grid[: args.sweep_points]
     for i, (s_, m_, h_) in enumerate(grid):
         f = Filter(k, s_, m_, h_, w["bits"])
-        if i == 0:  # warm-up of the first point's kernels
-            f.insert(d_ins, d_ioff)
-            f.query(d_q, d_qoff, out=d_out)
+        ti, tq = [], []
+        for rep in range(3):
             f.clear(torch.cuda.current_stream())
-        ev[0].record()
-        f.insert(d_ins, d_ioff)
-        ev[1].record()
-        f.query(d_q, d_qoff, out=d_out)
-        ev[2].record()
+            ev[0].record()
+            f.insert(d_ins, d_ioff)
+            ev[1].record()
+            f.query(d_q, d_qoff, out=d_out)
+            ev[2].record()
+            torch.cuda.synchronize()
+            ti.append(ev[0].elapsed_time(ev[1]))
+            tq.append(ev[1].elapsed_time(ev[2]))
         f.query(d_fn, out=d_fn_out)
         torch.cuda.synchronize()
         fp = int(d_out[neg0:].sum().item())
         no_fn = bool(int(d_fn_out.sum().item()) == fn_len - k + 1)
         rows.append({"s": s_, "m": m_, "H": h_, "fpr": fp / max(1, neg_kmers),
-                     "insert_ms": round(ev[0].elapsed_time(ev[1]), 4), "query_ms": round(ev[1].elapsed_time(ev[2]), 4),
+                     "insert_ms": round(float(np.median(ti)), 4), "query_ms": round(float(np.median(tq)), 4),
                      "variant": "rolling" if f.variant == 1 else "generic", "zero_fn": no_fn})
         f.close()
         if (i + 1) % 48 == 0:

@@ -169,6 +169,27 @@ int launch_shape(sbf_filter *f, uint32_t wgs_per_cu, hipStream_t st, sbf::Launch
   return SBF_OK;
 }
 
+}  // namespace
+
+int sbf::prepare_stream(sbf_filter *f, hipStream_t st) {
+  sbf::LaunchShape ls;
+  int rc = launch_shape(f, f->query_wgs_per_cu, st, ls);
+  if (rc == SBF_OK) rc = launch_shape(f, f->insert_wgs_per_cu, st, ls);
+  return rc;
+}
+
+void sbf::release_stream(sbf_filter *f, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(f->mu);
+  for (auto *m : {&f->queues, &f->starts}) {
+    auto it = m->find(st);
+    if (it == m->end()) continue;
+    if (it->second.ptr) (void)hipFree(it->second.ptr);
+    m->erase(it);
+  }
+}
+
+namespace {
+
 int run_insert(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::LaunchShape *given = nullptr) {
   const int mode = f->insert_mode == SBF_INSERT_ATOMIC ? sbf::kInsertAtomicMode : sbf::kInsertTwoPassMode;
   hipError_t e;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct sbf_filter;
+
 namespace sbf {
 
 struct Geometry {
@@ -57,6 +59,13 @@ hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const 
 // Record the calling thread's last error (code and message) for
 // sbf_last_error; returns code.
 int record_error(int code, const char *msg);
+
+// Allocate now the per-stream scratch a filter's launches on `stream` would
+// otherwise allocate on first use (work-queue counters), so that a latency-
+// sensitive caller does not pay a device allocation inside a request; and
+// free it when the stream goes away.
+int prepare_stream(sbf_filter *f, hipStream_t stream);
+void release_stream(sbf_filter *f, hipStream_t stream);
 
 // Utility kernels.
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t st);

@@ -81,8 +81,9 @@ namespace {
 int fail(int code, const std::string &msg) { return sbf::record_error(code, msg.c_str()); }
 int succeed() { return sbf::record_error(SBF_OK, ""); }
 
-void release_slot(Slot &s) {
+void release_slot(sbf_filter *f, Slot &s) {
   if (s.stream) (void)hipStreamSynchronize(s.stream);
+  if (s.stream && f) sbf::release_stream(f, s.stream);
   if (s.d_seq) (void)hipFree(s.d_seq);
   if (s.d_out) (void)hipFree(s.d_out);
   if (s.d_off) (void)hipFree(s.d_off);
@@ -234,10 +235,13 @@ sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases
     if (e == hipSuccess) e = hipMalloc((void **)&s.d_off, (slot_records + 1) * sizeof(uint64_t));
     if (e == hipSuccess) e = hipMalloc((void **)&s.d_starts, (slot_bases + 31) / 32 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_off, (slot_records + 1) * sizeof(uint64_t), 0);
+    // the filter's per-stream scratch for this slot, allocated now rather
+    // than inside the first request
+    if (e == hipSuccess && sbf::prepare_stream(f, s.stream) != SBF_OK) e = hipErrorOutOfMemory;
   }
   if (e != hipSuccess) {
     fail(e == hipErrorOutOfMemory ? SBF_E_NOMEM : SBF_E_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
-    for (Slot &s : sv->slots) release_slot(s);
+    for (Slot &s : sv->slots) release_slot(sv->f, s);
     delete sv;
     return nullptr;
   }
@@ -245,7 +249,7 @@ sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases
     sv->thread = std::thread(scheduler, sv);
   } catch (...) {
     fail(SBF_E_NOMEM, "scheduler thread");
-    for (Slot &s : sv->slots) release_slot(s);
+    for (Slot &s : sv->slots) release_slot(sv->f, s);
     delete sv;
     return nullptr;
   }
@@ -344,7 +348,7 @@ void sbf_server_destroy(sbf_server *sv) {
   }
   sv->cv_work.notify_all();
   if (sv->thread.joinable()) sv->thread.join();
-  for (Slot &s : sv->slots) release_slot(s);
+  for (Slot &s : sv->slots) release_slot(sv->f, s);
   for (auto &kv : sv->live) delete kv.second;
   delete sv;
 }
