@@ -53,10 +53,18 @@ __device__ __forceinline__ bool next_tile(const TileQueue &q, uint32_t *s_slot, 
   return tile < q.ntiles;
 }
 
+// Minimizer hash h_M of the m-mer at window position j (2m-bit value, first
+// base most significant; m <= 16 fits 32 bits).
 template <int M>
-__device__ __forceinline__ uint32_t mmer_at(const uint32_t *a, int j) {
-  static_assert(M >= 1 && M <= 16, "m-mers of the rolling kernels fit 32 bits");
-  return win32(a, j) >> (32 - 2 * M);
+__device__ __forceinline__ uint64_t mmer_hash(const uint32_t *a, int j) {
+  static_assert(M >= 1 && M <= 32, "m-mers fit 64 bits");
+  if constexpr (M <= 16) {
+    return minimizer_hash32(win32(a, j) >> (32 - 2 * M));
+  } else {
+    const uint32_t hi = win32(a, j) >> (64 - 2 * M);
+    const uint32_t lo = win32(a, j + M - 16);
+    return minimizer_hash(((uint64_t)hi << 32) | lo);
+  }
 }
 
 template <int S>
@@ -251,7 +259,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
       {
         uint64_t hb[W];
 #pragma unroll
-        for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
+        for (int i = 0; i < W; ++i) hb[i] = mmer_hash<M>(a, i);
         suf[W - 1] = hb[W - 1];
 #pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -269,7 +277,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
             if (i == 0) {
               mu = suf[0];
             } else {
-              hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+              hb[i - 1] = mmer_hash<M>(a, r + W - 1);
               pre = umin64(pre, hb[i - 1]);
               mu = umin64(suf[i], pre);
             }
@@ -313,7 +321,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
           }
         }
         if ((q + 1) * W < L) {
-          hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+          hb[W - 1] = mmer_hash<M>(a, (q + 1) * W + W - 1);
           suf[W - 1] = hb[W - 1];
 #pragma unroll
           for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -401,7 +409,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
       {
         uint64_t hb[W];
 #pragma unroll
-        for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
+        for (int i = 0; i < W; ++i) hb[i] = mmer_hash<M>(a, i);
         suf[W - 1] = hb[W - 1];
 #pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -418,7 +426,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
             if (i == 0) {
               mu = suf[0];
             } else {
-              hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+              hb[i - 1] = mmer_hash<M>(a, r + W - 1);
               pre = umin64(pre, hb[i - 1]);
               mu = umin64(suf[i], pre);
             }
@@ -426,7 +434,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
           }
         }
         if ((q + 1) * W < L) {
-          hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+          hb[W - 1] = mmer_hash<M>(a, (q + 1) * W + W - 1);
           suf[W - 1] = hb[W - 1];
 #pragma unroll
           for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -563,18 +571,17 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
       {
         uint64_t hb[W];
 #pragma unroll
-        for (int i = 0; i < W; ++i) hb[i] = minimizer_hash32(mmer_at<M>(a, i));
+        for (int i = 0; i < W; ++i) hb[i] = mmer_hash<M>(a, i);
         suf[W - 1] = hb[W - 1];
 #pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
       }
       auto test = [&](int r) {
-        // one three-input and-not-or per 32-bit half (v_bitop3 on gfx950)
         uint32_t miss = 0;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          miss = ((uint32_t)need[r][w] & ~(uint32_t)got[r][w]) | miss;
-          miss = ((uint32_t)(need[r][w] >> 32) & ~(uint32_t)(got[r][w] >> 32)) | miss;
+          const uint64_t m = need[r][w] & ~got[r][w];
+          miss |= (uint32_t)m | (uint32_t)(m >> 32);
         }
         const uint32_t present = (miss == 0 && ((kv >> r) & 1ull)) ? 1u : 0u;
         res[r >> 2] |= present << (8 * (r & 3));
@@ -591,7 +598,7 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
             if (i == 0) {
               mu = suf[0];
             } else {
-              hb[i - 1] = minimizer_hash32(mmer_at<M>(a, r + W - 1));
+              hb[i - 1] = mmer_hash<M>(a, r + W - 1);
               pre = umin64(pre, hb[i - 1]);
               mu = umin64(suf[i], pre);
             }
@@ -629,7 +636,7 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
           }
         }
         if ((q + 1) * W < L) {
-          hb[W - 1] = minimizer_hash32(mmer_at<M>(a, (q + 1) * W + W - 1));
+          hb[W - 1] = mmer_hash<M>(a, (q + 1) * W + W - 1);
           suf[W - 1] = hb[W - 1];
 #pragma unroll
           for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -727,23 +734,45 @@ hipError_t query_rolling(const uint64_t *words, uint32_t shard_mask, const SeqAr
 
 }  // namespace
 
+// Parameter sets (k, s, m, H) with compiled rolling kernels: the paper's
+// default and the neighbours its parameter study reports (Section
+// "Parameter Selection"); every other set runs the generic kernels.
+#define SBF_ROLLING_SETS(X) \
+  X(31, 28, 16, 4)          \
+  X(31, 27, 16, 4)          \
+  X(31, 30, 16, 4)          \
+  X(31, 31, 16, 4)          \
+  X(31, 28, 18, 4)          \
+  X(31, 28, 16, 8)
+
 bool rolling_supported(const Geometry &g) {
-  return g.shard_words == 4 && g.nshards <= (1ull << 32) && g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4;
+  if (g.shard_words != 4 || g.nshards > (1ull << 32)) return false;
+#define SBF_MATCH(K_, S_, M_, H_) \
+  if (g.k == K_ && g.s == S_ && g.m == M_ && g.H == H_) return true;
+  SBF_ROLLING_SETS(SBF_MATCH)
+#undef SBF_MATCH
+  return false;
 }
 
 hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode,
                                  const LaunchShape &ls, hipStream_t st) {
   const uint32_t mask = (uint32_t)(g.nshards - 1);
-  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4)
-    return insert_rolling<31, 28, 16, 4>(words, mask, a, mode, ls, st);
+#define SBF_CALL(K_, S_, M_, H_)                            \
+  if (g.k == K_ && g.s == S_ && g.m == M_ && g.H == H_) \
+    return insert_rolling<K_, S_, M_, H_>(words, mask, a, mode, ls, st);
+  SBF_ROLLING_SETS(SBF_CALL)
+#undef SBF_CALL
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, int mode,
                                 const LaunchShape &ls, hipStream_t st) {
   const uint32_t mask = (uint32_t)(g.nshards - 1);
-  if (g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4)
-    return query_rolling<31, 28, 16, 4>(words, mask, a, mode, ls, st);
+#define SBF_CALL(K_, S_, M_, H_)                            \
+  if (g.k == K_ && g.s == S_ && g.m == M_ && g.H == H_) \
+    return query_rolling<K_, S_, M_, H_>(words, mask, a, mode, ls, st);
+  SBF_ROLLING_SETS(SBF_CALL)
+#undef SBF_CALL
   return hipErrorInvalidValue;
 }
 

@@ -152,7 +152,7 @@ def test_generic_parameters(k, s, m, H):
     ins = noisy(rng, 20_000, 0.003)
     q = np.concatenate([ins[:7000], noisy(rng, 7000, 0.003)])
     print("case params", k, s, m, H, flush=True)
-    check((k, s, m, H, 1 << 16), [(ins, None)], (q, None))
+    check((k, s, m, H, 1 << 16), [(ins, None)], (q, None), variant="generic")
 
 
 def random_batch(rng, nrec, maxlen, p_invalid=0.0):
@@ -161,6 +161,37 @@ def random_batch(rng, nrec, maxlen, p_invalid=0.0):
     off = np.zeros(nrec + 1, dtype=np.uint64)
     off[1:] = np.cumsum(lens)
     return noisy(rng, int(off[-1]), p_invalid), off
+
+
+ROLLING_SETS = [(31, 27, 16, 4), (31, 30, 16, 4), (31, 31, 16, 4), (31, 28, 18, 4), (31, 28, 16, 8)]
+
+
+@pytest.mark.parametrize("k,s,m,H", ROLLING_SETS)
+def test_rolling_parameter_sets(k, s, m, H):
+    """The other compiled rolling parameter sets: every insert strategy and
+    query kernel against the oracle on a record batch spanning several tiles
+    with invalid bases and a ragged tail."""
+    rng = np.random.default_rng(k * 1000 + s * 100 + m * 10 + H)
+    ins = random_batch(rng, 60, 4000, 0.002)
+    q = random_batch(rng, 80, 3000, 0.002)
+    qs = np.concatenate([ins[0][: int(ins[1][20])], q[0]])
+    qo = np.concatenate([ins[1][:21], q[1][1:] + ins[1][20]])
+    params = (k, s, m, H, 1 << 15)
+    F, oa = oracle_run(params, [ins], (qs, qo))
+    print("case rolling set", k, s, m, H, flush=True)
+    for imode in (0, 1):
+        f = Filter(*params)
+        f.variant = VARIANTS["rolling"]
+        f.set_insert_mode(imode)
+        f.insert(dev(ins[0]), dev(ins[1].astype(np.uint64).view(np.int64)))
+        torch.cuda.synchronize()
+        assert_same(f.get_bits(), F, "filter words (insert mode %d)" % imode)
+        for qmode in (0, 1, 2):
+            f.set_query_mode(qmode)
+            ans = f.query(dev(qs), dev(qo.astype(np.uint64).view(np.int64)))
+            torch.cuda.synchronize()
+            assert_same(ans.cpu().numpy(), oa, "answers (query mode %d)" % qmode)
+        f.close()
 
 
 @pytest.mark.parametrize("variant", ["rolling", "generic"])
