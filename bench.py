@@ -302,6 +302,8 @@ def bench_served(args):
     rows = []
     for rate in [float(x) for x in args.rates.split(",")]:
         sv = Server(f, slots=args.slots, slot_bases=slot_bases, slot_records=slot_recs, max_pending=1 << 20)
+        if args.window_us:
+            sv.set_batch_window(args.window_us)
         gaps = rng.exponential(1.0 / rate, nreq)
         tickets = []
         start = time.perf_counter()
@@ -329,7 +331,8 @@ def bench_served(args):
     res = {"metric": "served form: query latency p50/p99 (ms) and k-mers/s under Poisson arrivals",
            "unit": "ms", "higher_is_better": False, "value": rows[0]["p50_ms"], "rates": rows,
            "config": {"workload": "served: %d bp genome resident, %d requests of 1..10000 reads" % (g[0].size, nreq),
-                      "filter_bits": f.num_bits, "slots": args.slots, "slot_bases": slot_bases}}
+                      "filter_bits": f.num_bits, "slots": args.slots, "slot_bases": slot_bases,
+                      "batch_window_us": args.window_us}}
     f.close()
     print(json.dumps(res), flush=True)
 
@@ -513,6 +516,7 @@ def main():
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000", help="served: offered requests/s")
     ap.add_argument("--requests", type=int, default=1000, help="served: requests per offered rate")
     ap.add_argument("--slots", type=int, default=4, help="served: server execution slots")
+    ap.add_argument("--window-us", type=int, default=0, help="served: batching window in microseconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="out_of_cache: skip the random-access probe")
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")

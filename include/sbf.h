@@ -236,6 +236,10 @@ int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint6
  * the next free slot, so batches overlap on the device.  While a server
  * exists, use the filter only through it (queries) or after destroying it.
  *
+ * sbf_server_set_batch_window: hold a free slot up to `microseconds` (at
+ * most 1 s; default 0) after the oldest pending request arrived, unless the
+ * pending requests already fill the slot, so that more requests join one
+ * batch: larger batches for up to that much added latency.
  * sbf_server_submit: one query request, a record batch in host memory (seq,
  * off with nrec+1 entries, off[0] = 0; out receives off[nrec] bytes as in
  * sbf_query_batch).  The buffers must stay valid and unchanged until the
@@ -254,6 +258,7 @@ int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint6
 typedef struct sbf_server sbf_server;
 sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases, uint64_t slot_records,
                               uint32_t max_pending);
+int sbf_server_set_batch_window(sbf_server *sv, uint64_t microseconds);
 int sbf_server_submit(sbf_server *sv, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out,
                       uint64_t *ticket);
 int sbf_server_poll(sbf_server *sv, uint64_t ticket);

@@ -71,6 +71,7 @@ struct sbf_server {
   std::deque<Request *> pending;
   std::unordered_map<uint64_t, Request *> live;
   uint64_t next_id = 1;
+  int64_t window_ns = 0;  // batching window (0: launch as soon as a slot is free)
   bool stop = false;
   std::thread thread;
   uint64_t batches = 0, requests_done = 0, bases_done = 0, max_batch_requests = 0;
@@ -164,6 +165,21 @@ void scheduler(sbf_server *sv) {
       std::vector<Request *> batch;
       {
         std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->pending.empty()) continue;
+        if (sv->window_ns > 0 && !sv->stop && now_ns() - sv->pending.front()->t_submit < sv->window_ns) {
+          // hold the slot for more requests unless the pending ones already fill it
+          uint64_t b = 0, n = 0;
+          bool fills = false;
+          for (const Request *r : sv->pending) {
+            if (b + r->bases > sv->cap_bases || n + r->nrec > sv->cap_records) {
+              fills = true;
+              break;
+            }
+            b += r->bases;
+            n += r->nrec;
+          }
+          if (!fills) continue;
+        }
         uint64_t bases = 0, recs = 0;
         while (!sv->pending.empty()) {
           Request *r = sv->pending.front();
@@ -255,6 +271,15 @@ sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases
   }
   succeed();
   return sv;
+}
+
+int sbf_server_set_batch_window(sbf_server *sv, uint64_t microseconds) {
+  if (!sv || microseconds > 1000000) return fail(SBF_E_INVAL, "server needed; window at most 1 s");
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->window_ns = (int64_t)microseconds * 1000;
+  }
+  return succeed();
 }
 
 int sbf_server_submit(sbf_server *sv, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out,

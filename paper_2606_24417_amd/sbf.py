@@ -69,6 +69,7 @@ SIGNATURES = {
     "sbf_graph_destroy": (None, [_vp]),
     "sbf_autotune": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64]),
     "sbf_server_create": (_vp, [_vp, _u32, _u64, _u64, _u32]),
+    "sbf_server_set_batch_window": (_int, [_vp, _u64]),
     "sbf_server_submit": (_int, [_vp, _vp, _vp, _u64, _vp, _vp]),
     "sbf_server_poll": (_int, [_vp, _u64]),
     "sbf_server_wait": (_int, [_vp, _u64, _vp, _vp]),
@@ -380,6 +381,10 @@ class Server:
         if hasattr(x, "data_ptr"):
             return ctypes.c_void_p(x.data_ptr())
         return x.ctypes.data_as(ctypes.c_void_p)
+
+    def set_batch_window(self, microseconds: int):
+        """Hold a free slot up to this long for more requests to join a batch."""
+        _check(lib().sbf_server_set_batch_window(self._h, int(microseconds)))
 
     def submit(self, seq, offsets, out) -> int:
         """Queue a query of a host record batch; out receives len(seq) bytes.

@@ -78,6 +78,7 @@ def test_server_rejects_bad_arguments_without_a_device(L):
     t = ctypes.c_uint64()
     assert L.sbf_server_submit(None, None, None, 0, None, ctypes.byref(t)) == sbf.SBF_E_INVAL
     assert L.sbf_server_poll(None, 1) == sbf.SBF_E_INVAL
+    assert L.sbf_server_set_batch_window(None, 10) == sbf.SBF_E_INVAL
     assert L.sbf_server_wait(None, 1, None, None) == sbf.SBF_E_INVAL
     L.sbf_server_destroy(None)
     assert L.sbf_graph_launch(None, None) == sbf.SBF_E_INVAL

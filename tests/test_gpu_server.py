@@ -72,8 +72,11 @@ def test_server_alone_and_in_mix_match_oracle(served):
         alone.append(out.numpy().copy())
     assert sv.stats()["max_batch_requests"] == 1
     sv.close()
-    # in the mix: four slots, requests submitted from two threads with jitter
+    # in the mix: four slots, requests submitted from two threads with jitter;
+    # a 2 ms batching window makes requests that arrive close together share
+    # a batch while earlier batches are still on the device
     sv = Server(f, slots=4, slot_bases=1 << 21, slot_records=1 << 12)
+    sv.set_batch_window(2000)
     for _, _, _, out in reqs:
         out.fill_(7)
     tickets = [None] * len(reqs)
