@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -254,6 +255,23 @@ sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases
     // the filter's per-stream scratch for this slot, allocated now rather
     // than inside the first request
     if (e == hipSuccess && sbf::prepare_stream(f, s.stream) != SBF_OK) e = hipErrorOutOfMemory;
+  }
+  // Run one tiny batch on every slot (a poly-A record of 64 bases): the first
+  // copies, kernels and event of a new stream carry one-time costs that would
+  // otherwise land on the first requests.
+  for (uint32_t i = 0; i < slots && e == hipSuccess; ++i) {
+    Slot &s = sv->slots[i];
+    const uint64_t n = 64, back = std::min<uint64_t>(n, (slot_records + 1) * sizeof(uint64_t));
+    s.h_off[0] = 0;
+    s.h_off[1] = n;
+    e = hipMemsetAsync(s.d_seq, 'A', n, s.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.d_off, s.h_off, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
+    if (e == hipSuccess && (sbf_mark_record_starts_dev(s.d_off, 1, n, s.d_starts, s.stream) != SBF_OK ||
+                            sbf_query_marked_dev(f, s.d_seq, n, s.d_starts, s.d_out, s.stream) != SBF_OK))
+      e = hipErrorLaunchFailure;
+    if (e == hipSuccess) e = hipMemcpyAsync(s.h_off, s.d_out, back, hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+    if (e == hipSuccess) e = hipEventSynchronize(s.done);
   }
   if (e != hipSuccess) {
     fail(e == hipErrorOutOfMemory ? SBF_E_NOMEM : SBF_E_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
