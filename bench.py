@@ -300,10 +300,20 @@ def bench_served(args):
     slot_bases = max(1 << 26, max(int(r[1][-1]) for r in reqs))
     slot_recs = max(1 << 16, max(r[1].size - 1 for r in reqs))
     rows = []
+    # one resident server for every rate, as in a serving process; its first
+    # requests (fresh buffers and streams) are an untimed warm-up
+    sv = Server(f, slots=args.slots, slot_bases=slot_bases, slot_records=slot_recs, max_pending=1 << 20)
+    if args.window_us:
+        sv.set_batch_window(args.window_us)
+    for seq, off, out in reqs[:32]:
+        sv.wait(sv.submit(seq, off, out))
+    tk = [sv.submit(seq, off, out) for seq, off, out in reqs[:32]]
+    for t in tk:
+        sv.wait(t)
+    prev = sv.stats()
     for rate in [float(x) for x in args.rates.split(",")]:
-        sv = Server(f, slots=args.slots, slot_bases=slot_bases, slot_records=slot_recs, max_pending=1 << 20)
-        if args.window_us:
-            sv.set_batch_window(args.window_us)
+        for i in range(len(ref)):
+            reqs[i][2].fill_(7)  # answers of this rate only
         gaps = rng.exponential(1.0 / rate, nreq)
         tickets = []
         start = time.perf_counter()
@@ -317,17 +327,20 @@ def bench_served(args):
         lat = [x[0] for x in waits]
         span = time.perf_counter() - start
         st = sv.stats()
-        sv.close()
+        batches = st["batches"] - prev["batches"]
+        prev = st
         ok = all(torch.equal(reqs[i][2], ref[i]) for i in range(len(ref)))
         row = {"offered_req_per_s": rate, "p50_ms": round(float(np.percentile(lat, 50)), 3),
                "p99_ms": round(float(np.percentile(lat, 99)), 3), "kmers_per_s": sum(req_kmers) / span,
-               "achieved_req_per_s": round(nreq / span, 1), "batches": st["batches"],
-               "max_batch_requests": st["max_batch_requests"], "answers_match_direct_query": ok,
+               "achieved_req_per_s": round(nreq / span, 1), "batches": batches,
+               "mean_batch_requests": round(nreq / max(1, batches), 2),
+               "max_batch_requests_so_far": st["max_batch_requests"], "answers_match_direct_query": ok,
                "p99_queue_ms": round(float(np.percentile([x[1] for x in waits], 99)), 3),
                "slowest": [{"ms": round(lat[i], 3), "queue_ms": round(waits[i][1], 3), "index": int(i),
                             "bases": int(reqs[i][1][-1])} for i in np.argsort(lat)[::-1][:3]]}
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
+    sv.close()
     res = {"metric": "served form: query latency p50/p99 (ms) and k-mers/s under Poisson arrivals",
            "unit": "ms", "higher_is_better": False, "value": rows[0]["p50_ms"], "rates": rows,
            "config": {"workload": "served: %d bp genome resident, %d requests of 1..10000 reads" % (g[0].size, nreq),

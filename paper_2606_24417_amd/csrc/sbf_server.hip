@@ -74,6 +74,8 @@ struct sbf_server {
   uint64_t next_id = 1;
   int64_t window_ns = 0;  // batching window (0: launch as soon as a slot is free)
   bool stop = false;
+  bool ready = false;               // the scheduler has warmed every slot
+  hipError_t warm_error = hipSuccess;
   std::thread thread;
   uint64_t batches = 0, requests_done = 0, bases_done = 0, max_batch_requests = 0;
 };
@@ -144,8 +146,39 @@ void finish(sbf_server *sv, std::vector<Request *> &reqs, int status, const std:
   sv->cv_done.notify_all();
 }
 
+// Run one tiny batch on every slot (a poly-A record of 64 bases) from the
+// scheduler thread: the first HIP calls of a thread and the first copies,
+// kernels and event of a new stream carry one-time costs that would otherwise
+// land on the first requests.
+hipError_t warm_slots(sbf_server *sv) {
+  hipError_t e = hipSuccess;
+  for (Slot &s : sv->slots) {
+    const uint64_t n = 64, back = std::min<uint64_t>(n, (sv->cap_records + 1) * sizeof(uint64_t));
+    s.h_off[0] = 0;
+    s.h_off[1] = n;
+    e = hipMemsetAsync(s.d_seq, 'A', n, s.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.d_off, s.h_off, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
+    if (e == hipSuccess && (sbf_mark_record_starts_dev(s.d_off, 1, n, s.d_starts, s.stream) != SBF_OK ||
+                            sbf_query_marked_dev(sv->f, s.d_seq, n, s.d_starts, s.d_out, s.stream) != SBF_OK))
+      e = hipErrorLaunchFailure;
+    if (e == hipSuccess) e = hipMemcpyAsync(s.h_off, s.d_out, back, hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+    if (e == hipSuccess) e = hipEventSynchronize(s.done);
+    if (e != hipSuccess) break;
+  }
+  return e;
+}
+
 void scheduler(sbf_server *sv) {
-  (void)hipSetDevice(sv->device);
+  hipError_t e = hipSetDevice(sv->device);
+  if (e == hipSuccess) e = warm_slots(sv);
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->warm_error = e;
+    sv->ready = true;
+  }
+  sv->cv_done.notify_all();
+  if (e != hipSuccess) return;
   for (;;) {
     bool progress = false;
     bool any_busy = false;
@@ -256,23 +289,6 @@ sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases
     // than inside the first request
     if (e == hipSuccess && sbf::prepare_stream(f, s.stream) != SBF_OK) e = hipErrorOutOfMemory;
   }
-  // Run one tiny batch on every slot (a poly-A record of 64 bases): the first
-  // copies, kernels and event of a new stream carry one-time costs that would
-  // otherwise land on the first requests.
-  for (uint32_t i = 0; i < slots && e == hipSuccess; ++i) {
-    Slot &s = sv->slots[i];
-    const uint64_t n = 64, back = std::min<uint64_t>(n, (slot_records + 1) * sizeof(uint64_t));
-    s.h_off[0] = 0;
-    s.h_off[1] = n;
-    e = hipMemsetAsync(s.d_seq, 'A', n, s.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.d_off, s.h_off, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
-    if (e == hipSuccess && (sbf_mark_record_starts_dev(s.d_off, 1, n, s.d_starts, s.stream) != SBF_OK ||
-                            sbf_query_marked_dev(f, s.d_seq, n, s.d_starts, s.d_out, s.stream) != SBF_OK))
-      e = hipErrorLaunchFailure;
-    if (e == hipSuccess) e = hipMemcpyAsync(s.h_off, s.d_out, back, hipMemcpyDeviceToHost, s.stream);
-    if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
-    if (e == hipSuccess) e = hipEventSynchronize(s.done);
-  }
   if (e != hipSuccess) {
     fail(e == hipErrorOutOfMemory ? SBF_E_NOMEM : SBF_E_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
     for (Slot &s : sv->slots) release_slot(sv->f, s);
@@ -283,6 +299,18 @@ sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases
     sv->thread = std::thread(scheduler, sv);
   } catch (...) {
     fail(SBF_E_NOMEM, "scheduler thread");
+    for (Slot &s : sv->slots) release_slot(sv->f, s);
+    delete sv;
+    return nullptr;
+  }
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [sv] { return sv->ready; });
+    e = sv->warm_error;
+  }
+  if (e != hipSuccess) {
+    sv->thread.join();
+    fail(SBF_E_DEVICE, std::string("server warm-up: ") + hipGetErrorString(e));
     for (Slot &s : sv->slots) release_slot(sv->f, s);
     delete sv;
     return nullptr;
