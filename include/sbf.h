@@ -217,8 +217,10 @@ void sbf_graph_destroy(sbf_graph *g);
 /* Autotuner: on the given device insert and query batches, time every insert
  * strategy and query organisation with one workgroup per tile and with
  * persistent grids of 1, 2, 4 and 8 workgroups per CU (median of three runs
- * after a warm-up; inserts go to a scratch filter of the same geometry, so f
- * is not modified), then apply the fastest settings to f.  A text report of
+ * after a warm-up) on f itself, whose words are first saved to a temporary
+ * device buffer of the filter's size and restored afterwards (f's contents
+ * are unchanged; the buffer must fit in device memory), then apply the
+ * fastest settings to f.  A text report of
  * every timing is written to report (NUL-terminated, truncated to
  * report_len; may be NULL).  Synchronous. */
 int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec,

@@ -892,13 +892,26 @@ int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint6
   if (!use_rolling(f)) {
     line("generic kernels: nothing to tune\n");
   } else {
-    // a scratch filter of the same geometry takes the inserts
-    sbf_filter *t = sbf_create(f->g.k, f->g.s, f->g.m, f->g.H, sbf_num_bits(f));
-    if (!t) return g_err;
-    Scratch si, sq, out;
+    // The trials run on the filter itself, so that they see its own memory
+    // (a second filter-sized allocation can be mapped differently and time
+    // differently out of cache); its words are saved first and put back after.
+    sbf_filter *t = f;
+    Scratch si, sq, out, saved;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStream_t st = t->stream;
-    rc = grow(si, (ins_len + 31) / 32 * 4, "record-start bits");
+    const int keep_imode = f->insert_mode, keep_qmode = f->query_mode;
+    const uint32_t keep_iw = f->insert_wgs_per_cu, keep_qw = f->query_wgs_per_cu;
+    SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
+    bool backed_up = false;
+    rc = grow(saved, sbf_num_words(f) * sizeof(uint64_t), "filter backup");
+    if (!rc) {
+      if (hipMemcpyAsync(saved.ptr, f->words, sbf_num_words(f) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st) ==
+          hipSuccess)
+        backed_up = true;
+      else
+        rc = set_error(SBF_E_DEVICE, "filter backup copy");
+    }
+    if (!rc) rc = grow(si, (ins_len + 31) / 32 * 4, "record-start bits");
     if (!rc) rc = grow(sq, (q_len + 31) / 32 * 4, "record-start bits");
     if (!rc) rc = grow(out, q_len, "autotune answers");
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
@@ -968,11 +981,19 @@ int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint6
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    // put the filter's words back
+    if (backed_up && hipMemcpyAsync(f->words, saved.ptr, sbf_num_words(f) * sizeof(uint64_t),
+                                    hipMemcpyDeviceToDevice, st) != hipSuccess && !rc)
+      rc = set_error(SBF_E_DEVICE, "filter restore copy");
     (void)hipStreamSynchronize(st);
     free_scratch(si);
     free_scratch(sq);
     free_scratch(out);
-    sbf_destroy(t);
+    free_scratch(saved);
+    f->insert_mode = keep_imode;
+    f->query_mode = keep_qmode;
+    f->insert_wgs_per_cu = keep_iw;
+    f->query_wgs_per_cu = keep_qw;
     if (rc) return rc;
     f->insert_mode = bi_mode;
     f->insert_wgs_per_cu = bi_shape;
