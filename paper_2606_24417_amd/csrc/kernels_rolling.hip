@@ -512,7 +512,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
 // Answers are packed four per register and written as 16-byte stores.
 // ---------------------------------------------------------------------------
 template <int K, int S, int M, int H, int L, int WG, int D>
-__global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void query_lane_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                         const uint32_t *__restrict__ starts, int aligned16,
                                                         const uint64_t *__restrict__ words, uint32_t shard_mask,
                                                         uint8_t *__restrict__ out, uint64_t n_out,
@@ -527,6 +527,12 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
 
   __shared__ uint32_t s_codes[NGRAN];
   __shared__ uint32_t s_vb[NGRAN];
+  // van Herk state of each lane in LDS (structure of arrays, lane-minor):
+  // slot i holds the suffix minimum i of the current block until step i has
+  // used it, then the hash of position i of the next block.  Keeping these 32
+  // 64-bit values out of registers lets the kernel run four waves per SIMD
+  // (at most 128 VGPRs; 37 KB of LDS per workgroup, four workgroups per CU).
+  __shared__ uint64_t s_vh[W][WG];
 
   __shared__ uint32_t s_next_tile;
   uint64_t tile;
@@ -567,14 +573,16 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
 #pragma unroll
           for (int w = 0; w < 4; ++w) pr[j][w] = oh[j][w] | oh[j + 1][w];
       }
-      uint64_t suf[W];
+      const int t = threadIdx.x;
       {
-        uint64_t hb[W];
+        // suffix minima of block 0
+        uint64_t m = mmer_hash<M>(a, W - 1);
+        s_vh[W - 1][t] = m;
 #pragma unroll
-        for (int i = 0; i < W; ++i) hb[i] = mmer_hash<M>(a, i);
-        suf[W - 1] = hb[W - 1];
-#pragma unroll
-        for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+        for (int i = W - 2; i >= 0; --i) {
+          m = umin64(mmer_hash<M>(a, i), m);
+          s_vh[i][t] = m;
+        }
       }
       auto test = [&](int r) {
         uint32_t miss = 0;
@@ -588,7 +596,6 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
       };
 #pragma unroll
       for (int q = 0; q * W < L; ++q) {
-        uint64_t hb[W];
         uint64_t pre = ~0ull;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
@@ -596,11 +603,12 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
           if (r < L) {
             uint64_t mu;
             if (i == 0) {
-              mu = suf[0];
+              mu = s_vh[0][t];
             } else {
-              hb[i - 1] = mmer_hash<M>(a, r + W - 1);
-              pre = umin64(pre, hb[i - 1]);
-              mu = umin64(suf[i], pre);
+              const uint64_t h = mmer_hash<M>(a, r + W - 1);  // position i-1 of block q+1
+              pre = umin64(pre, h);
+              mu = umin64(s_vh[i][t], pre);
+              s_vh[i - 1][t] = h;  // slot i-1 was last read at step i-1
             }
             // A lane loads its shard only where the shard changes (about once
             // per super-k-mer); elsewhere it reads shard 0, one line shared by
@@ -636,10 +644,14 @@ __global__ __launch_bounds__(WG) void query_lane_kernel(const uint8_t *__restric
           }
         }
         if ((q + 1) * W < L) {
-          hb[W - 1] = mmer_hash<M>(a, (q + 1) * W + W - 1);
-          suf[W - 1] = hb[W - 1];
+          // suffix minima of block q+1, in place over its hashes
+          uint64_t m = mmer_hash<M>(a, (q + 1) * W + W - 1);
+          s_vh[W - 1][t] = m;
 #pragma unroll
-          for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
+          for (int i = W - 2; i >= 0; --i) {
+            m = umin64(s_vh[i][t], m);
+            s_vh[i][t] = m;
+          }
         }
       }
 #pragma unroll
