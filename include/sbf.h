@@ -172,9 +172,9 @@ int sbf_set_insert_mode(sbf_filter *f, int mode);
 
 /* How the rolling query kernel is organised:
  *   SBF_QUERY_LANE (default): each lane walks 32 consecutive k-mers, builds
- *     the mask of each k-mer's (k-s+1)*H bits from its s-mers, loads the
- *     k-mer's shard and tests the mask two k-mers later; consecutive k-mers
- *     of one super-k-mer reuse the cached shard;
+ *     the mask of each k-mer's (k-s+1)*H bits from its s-mers and tests it
+ *     one k-mer later against the k-mer's shard, which the lane loads only
+ *     where the shard changes (once per super-k-mer);
  *   SBF_QUERY_LEADER: a first pass stores shards and bit addresses in LDS, a
  *     second tests one k-mer per lane; the first lane of each run of equal
  *     shards loads the 32-byte shard and the run's other lanes receive it by

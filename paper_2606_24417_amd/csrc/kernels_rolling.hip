@@ -9,14 +9,18 @@
 //   * consecutive valid k-mers with the same shard form a segment (the
 //     super-k-mer of Section "Minimizers and Super-k-mers", split where the
 //     shard changes); the lane ORs the one-hot masks of the segment's s-mers
-//     in registers and issues one 64-bit atomic OR per word when the segment
-//     ends - the per-lane form of the paper's segmented reduction with the
-//     run head doing the atomics (Algorithm 1);
-//   * the query computes every k-mer's shard and the bit addresses of every
-//     s-mer in the same way, stages them in LDS, and then tests k-mers with
-//     one lane per k-mer: the first lane of each run of equal shards in the
-//     wave loads the 32-byte shard and the other lanes of the run read it with
-//     ds_bpermute (the paper's leader load and broadcast, Algorithm 2).
+//     in registers and writes the segment's shard once when it ends - the
+//     per-lane form of the paper's segmented reduction (Algorithm 1) - either
+//     as four 64-bit atomic ORs or, by default, as a plain read-OR-write
+//     followed by a second pass that atomically restores any bit a racing
+//     write dropped;
+//   * the default query (query_lane_kernel) walks k-mers the same way, builds
+//     each k-mer's mask of (k-s+1)*H bits and tests it against the k-mer's
+//     shard, which a lane loads once per run of equal shards (the paper's
+//     shard sharing, Algorithm 2); query_rolling_kernel instead stages shards
+//     and bit addresses in LDS and tests one k-mer per lane, the first lane of
+//     each run of equal shards loading the shard for the others (leader load
+//     and ds_bpermute broadcast).
 // Every result is bit-identical to the per-k-mer definition: OR is
 // commutative and idempotent, and a k-mer is tested in its own shard.
 #include "sbf_device.h"
