@@ -13,7 +13,9 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <unordered_map>
+#include <vector>
 
 using sbf::Geometry;
 using sbf::SeqArgs;
@@ -308,12 +310,41 @@ int ensure_pipe(sbf_filter *f) {
   return SBF_OK;
 }
 
+// Host copy between pageable and pinned memory, split over up to 8 threads
+// for large buffers (one thread copies at well under the host link's rate).
+void host_copy(void *dst, const void *src, size_t n) {
+  constexpr size_t kPerThread = 8ull << 20;
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t parts = std::min<size_t>(std::min<size_t>(8, hw), n / kPerThread);
+  if (parts < 2) {
+    memcpy(dst, src, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const size_t step = (n / parts + 4095) & ~size_t(4095);
+  try {
+    for (size_t i = 1; i < parts && i * step < n; ++i) {
+      const size_t a = i * step, b = std::min(n, a + step);
+      th.emplace_back([=] { memcpy((char *)dst + a, (const char *)src + a, b - a); });
+    }
+  } catch (...) {
+    // no thread available: the remaining parts are copied below
+  }
+  const size_t done_by_threads = th.size();
+  memcpy(dst, src, std::min(n, step));
+  for (size_t i = done_by_threads + 1; i < parts && i * step < n; ++i) {
+    const size_t a = i * step, b = std::min(n, a + step);
+    memcpy((char *)dst + a, (const char *)src + a, b - a);
+  }
+  for (auto &t : th) t.join();
+}
+
 // Wait for a stage's last chunk and move its answers to the caller's buffer.
 int finish_slot(PipeSlot &ps) {
   if (!ps.pending) return SBF_OK;
   ps.pending = false;
   SBF_HIP(hipEventSynchronize(ps.done), "kernel execution");
-  if (ps.flush_dst && ps.flush_len) memcpy(ps.flush_dst, ps.h_out.ptr, ps.flush_len);
+  if (ps.flush_dst && ps.flush_len) host_copy(ps.flush_dst, ps.h_out.ptr, ps.flush_len);
   ps.flush_dst = nullptr;
   ps.flush_len = 0;
   return SBF_OK;
@@ -370,7 +401,7 @@ int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nre
     const char *src = seq + c0;
     if (!in_direct) {
       if ((rc = grow_pinned(ps.h_seq, budget + 64, "pinned staging buffer"))) return drain_pipe(f, rc);
-      memcpy(ps.h_seq.ptr, src, len);
+      host_copy(ps.h_seq.ptr, src, len);
       src = (const char *)ps.h_seq.ptr;
     }
     hipError_t e = hipMemcpyAsync(ps.d_seq.ptr, src, len, hipMemcpyHostToDevice, st);
