@@ -494,6 +494,27 @@ def bench_sweep(args):
         f.close()
         if (i + 1) % 48 == 0:
             print("[bench] sweep %d/%d points" % (i + 1, len(grid)), file=sys.stderr, flush=True)
+    # shard geometry (4, 8, 16 words per shard) at (28, 16, 4): generic kernels
+    # for all three so that their times compare, plus the rolling kernels at 4
+    geometry = []
+    for S, variant in ((4, 1), (4, 2), (8, 2), (16, 2)):
+        f = Filter(k, 28, 16, 4, w["bits"], shard_words=S)
+        f.variant = variant
+        ti, tq = [], []
+        for rep in range(3):
+            f.clear(torch.cuda.current_stream())
+            ev[0].record()
+            f.insert(d_ins, d_ioff)
+            ev[1].record()
+            f.query(d_q, d_qoff, out=d_out)
+            ev[2].record()
+            torch.cuda.synchronize()
+            ti.append(ev[0].elapsed_time(ev[1]))
+            tq.append(ev[1].elapsed_time(ev[2]))
+        geometry.append({"shard_words": S, "kernels": "rolling" if variant == 1 else "generic",
+                         "filter_bits": f.num_bits, "fpr": int(d_out[neg0:].sum().item()) / max(1, neg_kmers),
+                         "insert_ms": round(float(np.median(ti)), 4), "query_ms": round(float(np.median(tq)), 4)})
+        f.close()
     # FPR of independent random 31-mers against filter size, (28, 16, 4)
     n_rand = int(10_000_000 * min(1.0, args.scale * 10))
     rs = synth.uniform_acgt(31 * n_rand, 211)  # uniform bases, as the Bloom closed form assumes
@@ -517,7 +538,7 @@ def bench_sweep(args):
            "unit": "fpr", "points": len(rows), "zero_false_negatives_everywhere": all_ok,
            "best_fpr": best, "fastest": fastest,
            "at_28_16_4": next((r for r in rows if (r["s"], r["m"], r["H"]) == (28, 16, 4)), None),
-           "rows": rows, "fpr_vs_size": curve, "random_kmers": n_rand,
+           "rows": rows, "geometry": geometry, "fpr_vs_size": curve, "random_kmers": n_rand,
            "config": {"workload": w["name"] + " (scale %g)" % args.scale, "filter_bits": w["bits"],
                       "insert_kmers": n_ins_kmers, "query_kmers": n_q_kmers, "negative_kmers": neg_kmers}}
     print(json.dumps(res), flush=True)

@@ -69,6 +69,18 @@ typedef struct sbf_filter sbf_filter; /* opaque; owns its device bit array */
  * on failure. */
 sbf_filter *sbf_create(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits);
 
+/* As sbf_create, with shards of shard_words 64-bit words (4, 8 or 16; the
+ * paper's shard is 4 words = 256 bits, and sbf_create uses 4).  Hash index t
+ * still writes sector t mod 4; a shard of S words holds S/4 groups of the
+ * four sectors, and the group of index t is taken from the log2(S/4) bits of
+ * the s-mer hash just above the t-th 6-bit bit address, which needs
+ * 64/H >= 6 + log2(S/4) (H <= 9 for S = 8, H <= 8 for S = 16).  The shard
+ * count is the power of two at or above ceil(bits / (64 S)).  Filters with
+ * S = 8 or 16 run the generic kernels; bits and answers differ from S = 4,
+ * so S is part of the filter's definition, not a tuning setting.  Errors as
+ * sbf_create. */
+sbf_filter *sbf_create_ex(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits, uint32_t shard_words);
+
 /* Free the filter and its device memory after waiting for its stream.
  * sbf_destroy(NULL) does nothing. */
 void sbf_destroy(sbf_filter *f);

@@ -467,10 +467,22 @@ int validate_offsets(const uint64_t *off, uint64_t nrec) {
 extern "C" {
 
 sbf_filter *sbf_create(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits) {
+  return sbf_create_ex(k, s, m, H, bits, 4);
+}
+
+sbf_filter *sbf_create_ex(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits, uint32_t shard_words) {
   if (k < 1 || k > 32 || s < 1 || s > k || m < 1 || m > k || H < 1 || H > 16 || bits < 1 || bits > kMaxBits) {
     set_error(SBF_E_INVAL,
               "invalid parameters k=%u s=%u m=%u H=%u bits=%llu (need 1<=s,m<=k<=32, 1<=H<=16, 1<=bits<=2^40)", k, s,
               m, H, (unsigned long long)bits);
+    return nullptr;
+  }
+  // shard geometry: 4, 8 or 16 words; a wider shard takes its word group from
+  // the log2(S/4) bits above each 6-bit address, which must fit the slice
+  const uint32_t extra = shard_words == 16 ? 2 : shard_words == 8 ? 1 : 0;
+  if ((shard_words != 4 && shard_words != 8 && shard_words != 16) || (extra && 64 / H < 6 + extra)) {
+    set_error(SBF_E_INVAL, "invalid shard geometry: %u words with H=%u (need 4, 8 or 16 words, and 64/H >= %u)",
+              shard_words, H, 6 + extra);
     return nullptr;
   }
   sbf_filter *f = new (std::nothrow) sbf_filter;
@@ -482,8 +494,9 @@ sbf_filter *sbf_create(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t 
   f->g.s = s;
   f->g.m = m;
   f->g.H = H;
-  f->g.shard_words = 4;
-  f->g.nshards = next_pow2(std::max<uint64_t>(1, (bits + 255) / 256));
+  f->g.shard_words = shard_words;
+  const uint64_t per_shard = 64ull * shard_words;
+  f->g.nshards = next_pow2(std::max<uint64_t>(1, (bits + per_shard - 1) / per_shard));
   hipError_t e = hipGetDevice(&f->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&f->num_cus, hipDeviceAttributeMultiprocessorCount, f->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking);

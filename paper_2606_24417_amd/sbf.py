@@ -37,6 +37,7 @@ _u64 = ctypes.c_uint64
 _int = ctypes.c_int
 SIGNATURES = {
     "sbf_create": (_vp, [_u32, _u32, _u32, _u32, _u64]),
+    "sbf_create_ex": (_vp, [_u32, _u32, _u32, _u32, _u64, _u32]),
     "sbf_destroy": (None, [_vp]),
     "sbf_insert_seq": (_int, [_vp, _vp, _u64]),
     "sbf_query_seq": (_int, [_vp, _vp, _u64, _vp]),
@@ -138,9 +139,10 @@ def _stream_handle(stream):
 class Filter:
     """A Super Bloom filter on the current GPU (owns its device bit array)."""
 
-    def __init__(self, k=31, s=28, m=16, H=4, bits=1 << 24):
+    def __init__(self, k=31, s=28, m=16, H=4, bits=1 << 24, shard_words=4):
         self.k, self.s, self.m, self.H = int(k), int(s), int(m), int(H)
-        h = lib().sbf_create(self.k, self.s, self.m, self.H, int(bits))
+        self.shard_words = int(shard_words)
+        h = lib().sbf_create_ex(self.k, self.s, self.m, self.H, int(bits), self.shard_words)
         if not h:
             code, msg = last_error()
             raise SBFError(code, msg)

@@ -56,6 +56,15 @@ def test_create_rejects_bad_parameters(L, k, s, m, H, bits):
     assert code == sbf.SBF_E_INVAL and "invalid parameters" in msg
 
 
+@pytest.mark.parametrize("H,S", [(4, 5), (4, 0), (4, 32), (10, 8), (9, 16), (16, 8)])
+def test_create_ex_rejects_bad_geometry(L, H, S):
+    from paper_2606_24417_amd import sbf
+
+    assert L.sbf_create_ex(31, 28, 16, H, 1 << 20, S) is None
+    code, msg = sbf.last_error()
+    assert code == sbf.SBF_E_INVAL and "shard geometry" in msg
+
+
 def test_null_filter_calls_fail_cleanly(L):
     from paper_2606_24417_amd import sbf
 
