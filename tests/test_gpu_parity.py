@@ -349,6 +349,44 @@ def test_nondefault_stream_and_state_roundtrip():
     g.close()
 
 
+@pytest.mark.parametrize("qmode", [0, 1])
+def test_concurrent_streams(qmode):
+    """One filter, three streams: a record-batch insert on one, then two query
+    batches on two others ordered after it by an event and free to overlap
+    each other (each stream has its own record-start and work-queue
+    scratch).  Every answer against the oracle."""
+    rng = np.random.default_rng(31 + qmode)
+    ins = random_batch(rng, 200, 3000, 0.002)
+    qa = random_batch(rng, 300, 2000, 0.002)
+    qb = random_batch(rng, 150, 5000, 0.002)
+    params = HOT + (1 << 18,)
+    F, oa = oracle_run(params, [ins], qa)
+    ob = oracle.query(oracle.Params(*params), F, qb[0], qb[1])
+    print("case streams", qmode, flush=True)
+    f = Filter(*params)
+    f.set_query_mode(qmode)
+    s_ins, s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    d_ins, d_ioff = dev(ins[0]), dev(ins[1].astype(np.uint64).view(np.int64))
+    d_qa, d_qao = dev(qa[0]), dev(qa[1].astype(np.uint64).view(np.int64))
+    d_qb, d_qbo = dev(qb[0]), dev(qb[1].astype(np.uint64).view(np.int64))
+    out_a = torch.full((qa[0].size,), 7, dtype=torch.uint8, device="cuda")
+    out_b = torch.full((qb[0].size,), 7, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    done = torch.cuda.Event()
+    f.insert(d_ins, d_ioff, stream=s_ins)
+    done.record(s_ins)
+    s_a.wait_event(done)
+    s_b.wait_event(done)
+    for _ in range(3):  # repeated, so that the two query streams interleave
+        f.query(d_qa, d_qao, out=out_a, stream=s_a)
+        f.query(d_qb, d_qbo, out=out_b, stream=s_b)
+    torch.cuda.synchronize()
+    assert_same(f.get_bits(), F, "filter words")
+    assert_same(out_a.cpu().numpy(), oa, "answers on stream a")
+    assert_same(out_b.cpu().numpy(), ob, "answers on stream b")
+    f.close()
+
+
 @pytest.mark.parametrize("H", [1, 2, 4, 8])
 def test_all_A_closed_form(H):
     f = Filter(31, 28, 16, H, 1 << 20)
