@@ -8,6 +8,14 @@
 // in the queue and join the next batch of the first slot that frees up, so
 // the copies and kernels of different batches overlap on the device.  The
 // server uses the filter only through the public stream-ordered entry points.
+//
+// Requests whose sequence and answer buffers are 16-byte aligned pinned host
+// memory that the device can address are moved by the server's own kernels
+// (a gather of every such request's bases into the slot's device buffer, a
+// scatter of answers back), reading and writing host memory directly; other
+// requests use hipMemcpyAsync.  The runtime's copy engines can stall a
+// host-to-device copy for milliseconds after an idle period, which is what
+// the kernels avoid.
 #include "sbf.h"
 #include "sbf_internal.h"
 
@@ -41,11 +49,100 @@ struct Request {
   uint64_t nrec = 0;
   uint8_t *out = nullptr;
   uint64_t bases = 0;
+  bool direct_in = false, direct_out = false;  // moved by the server's kernels
   int64_t t_submit = 0, t_start = 0, t_done = 0;
   int state = kPending;
   int status = SBF_OK;
   std::string error;
 };
+
+// One request of a batch for the copy kernels.  The table lives in the slot's
+// pinned memory and the kernels read it from there.
+struct CopyDesc {
+  const uint8_t *src;  // the caller's bases when they are moved by the gather, else null
+  uint8_t *dst;        // the caller's answer buffer when the scatter writes it, else null
+  uint64_t base;       // 16-byte aligned offset of the request in the slot's device buffers
+  uint64_t n;          // bases
+  uint64_t end;        // 16-byte aligned end; bytes [base + n, end) are padding
+};
+
+constexpr uint32_t kPad4 = 0x4E4E4E4Eu;  // "NNNN": padding bases are invalid
+
+// Bases into the slot buffer: full 16-byte chunks of directly moved requests
+// with 16-byte loads from host memory, the chunk holding the last bases byte
+// by byte, and padding as 'N'.  Requests copied by the runtime only get their
+// padding.  Block row y walks requests y, y + gridDim.y, ...
+__global__ __launch_bounds__(256) void gather_kernel(const CopyDesc *desc, uint32_t nreq, uint8_t *dev) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.y; i < nreq; i += gridDim.y) {
+    const CopyDesc d = desc[i];
+    const uint64_t nch = (d.end - d.base) >> 4;
+    const uint64_t cfull = d.n >> 4;
+    const uint32_t keep = (uint32_t)(d.n & 15);
+    for (uint64_t c = (d.src ? 0 : cfull) + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += stride) {
+      uint8_t *o = dev + d.base + 16 * c;
+      if (c < cfull) {
+        *reinterpret_cast<uint4 *>(o) = *reinterpret_cast<const uint4 *>(d.src + 16 * c);
+      } else if (c == cfull && keep) {
+        if (d.src) {
+          uint32_t w[4] = {kPad4, kPad4, kPad4, kPad4};
+          for (uint32_t j = 0; j < keep; ++j) {
+            const uint32_t sh = 8 * (j & 3);
+            w[j >> 2] = (w[j >> 2] & ~(0xFFu << sh)) | ((uint32_t)d.src[16 * c + j] << sh);
+          }
+          *reinterpret_cast<uint4 *>(o) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
+          for (uint32_t j = keep; j < 16; ++j) o[j] = (uint8_t)'N';
+        }
+      } else {
+        *reinterpret_cast<uint4 *>(o) = make_uint4(kPad4, kPad4, kPad4, kPad4);
+      }
+    }
+  }
+}
+
+// Answers back into the callers' buffers for directly moved requests:
+// 16-byte stores for full chunks, byte stores for the last bytes; nothing
+// outside [dst, dst + n) is written.
+__global__ __launch_bounds__(256) void scatter_kernel(const CopyDesc *desc, uint32_t nreq, const uint8_t *dev) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.y; i < nreq; i += gridDim.y) {
+    const CopyDesc d = desc[i];
+    if (!d.dst) continue;
+    const uint64_t cfull = d.n >> 4;
+    const uint64_t nch = (d.n + 15) >> 4;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nch; c += stride) {
+      const uint8_t *in = dev + d.base + 16 * c;
+      if (c < cfull) {
+        *reinterpret_cast<uint4 *>(d.dst + 16 * c) = *reinterpret_cast<const uint4 *>(in);
+      } else {
+        for (uint32_t j = 0; j < (uint32_t)(d.n & 15); ++j) d.dst[16 * c + j] = in[j];
+      }
+    }
+  }
+}
+
+hipError_t launch_copy(bool gather, const CopyDesc *desc, uint32_t nreq, uint8_t *dev, hipStream_t st) {
+  if (nreq == 0) return hipSuccess;
+  const dim3 grid(64, std::min<uint32_t>(nreq, 65535u));
+  if (gather)
+    hipLaunchKernelGGL(gather_kernel, grid, dim3(256), 0, st, desc, nreq, dev);
+  else
+    hipLaunchKernelGGL(scatter_kernel, grid, dim3(256), 0, st, desc, nreq, (const uint8_t *)dev);
+  return hipGetLastError();
+}
+
+// True when p is 16-byte aligned pinned host memory that the device addresses
+// with the same pointer.
+bool device_view(const void *p) {
+  if (!p || ((uintptr_t)p & 15u)) return false;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeHost && at.devicePointer == p;
+}
 
 struct Slot {
   hipStream_t stream = nullptr;
@@ -55,6 +152,9 @@ struct Slot {
   uint64_t *d_off = nullptr;
   uint32_t *d_starts = nullptr;
   uint64_t *h_off = nullptr;  // pinned; reused once the slot's event has completed
+  CopyDesc *h_desc = nullptr;  // pinned copy descriptors, one per request of a batch
+  const uint64_t *dv_off = nullptr;  // device addresses of h_off and h_desc
+  const CopyDesc *dv_desc = nullptr;
   std::vector<Request *> reqs;
   bool busy = false;
 };
@@ -93,36 +193,49 @@ void release_slot(sbf_filter *f, Slot &s) {
   if (s.d_off) (void)hipFree(s.d_off);
   if (s.d_starts) (void)hipFree(s.d_starts);
   if (s.h_off) (void)hipHostFree(s.h_off);
+  if (s.h_desc) (void)hipHostFree(s.h_desc);
   if (s.done) (void)hipEventDestroy(s.done);
   if (s.stream) (void)hipStreamDestroy(s.stream);
   s = Slot();
 }
 
-// Issue one batch on a free slot.  Returns an error message or "".
+// Issue one batch on a free slot.  Returns an error message or "".  Each
+// request starts at a 16-byte aligned offset of the slot buffers; the padding
+// before the next request ('N' bases) extends the previous request's last
+// record, where it only adds invalid k-mers whose answers are not returned.
 std::string launch_batch(sbf_server *sv, Slot &s, const std::vector<Request *> &batch) {
   uint64_t base = 0, rec = 0;
+  uint32_t i = 0;
   hipError_t e = hipSuccess;
   for (Request *r : batch) {
-    e = hipMemcpyAsync(s.d_seq + base, r->seq, r->bases, hipMemcpyHostToDevice, s.stream);
-    if (e != hipSuccess) return std::string("copy to device: ") + hipGetErrorString(e);
-    for (uint64_t i = 0; i < r->nrec; ++i) s.h_off[rec + i] = base + r->off[i];
+    const uint64_t end = (base + r->bases + 15) & ~15ull;
+    s.h_desc[i++] = CopyDesc{r->direct_in ? (const uint8_t *)r->seq : nullptr, r->direct_out ? r->out : nullptr,
+                             base, r->bases, end};
+    if (!r->direct_in) {
+      e = hipMemcpyAsync(s.d_seq + base, r->seq, r->bases, hipMemcpyHostToDevice, s.stream);
+      if (e != hipSuccess) return std::string("copy to device: ") + hipGetErrorString(e);
+    }
+    for (uint64_t j = 0; j < r->nrec; ++j) s.h_off[rec + j] = base + r->off[j];
     rec += r->nrec;
-    base += r->bases;
+    base = end;
   }
   s.h_off[rec] = base;
-  e = hipMemcpyAsync(s.d_off, s.h_off, (rec + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
-  if (e != hipSuccess) return std::string("copy offsets: ") + hipGetErrorString(e);
+  e = launch_copy(true, s.dv_desc, i, (uint8_t *)s.d_seq, s.stream);
+  if (e != hipSuccess) return std::string("gather kernel: ") + hipGetErrorString(e);
   const char *msg = nullptr;
-  if (sbf_mark_record_starts_dev(s.d_off, rec, base, s.d_starts, s.stream) != SBF_OK ||
+  // the marking kernel reads the offsets straight from the slot's pinned table
+  if (sbf_mark_record_starts_dev(s.dv_off, rec, base, s.d_starts, s.stream) != SBF_OK ||
       sbf_query_marked_dev(sv->f, s.d_seq, base, s.d_starts, s.d_out, s.stream) != SBF_OK) {
     sbf_last_error(&msg);
     return std::string("query: ") + (msg ? msg : "");
   }
-  uint64_t at = 0;
-  for (Request *r : batch) {
-    e = hipMemcpyAsync(r->out, s.d_out + at, r->bases, hipMemcpyDeviceToHost, s.stream);
+  e = launch_copy(false, s.dv_desc, i, s.d_out, s.stream);
+  if (e != hipSuccess) return std::string("scatter kernel: ") + hipGetErrorString(e);
+  for (uint32_t j = 0; j < i; ++j) {
+    const Request *r = batch[j];
+    if (r->direct_out) continue;
+    e = hipMemcpyAsync(r->out, s.d_out + s.h_desc[j].base, r->bases, hipMemcpyDeviceToHost, s.stream);
     if (e != hipSuccess) return std::string("copy to host: ") + hipGetErrorString(e);
-    at += r->bases;
   }
   e = hipEventRecord(s.done, s.stream);
   if (e != hipSuccess) return std::string("event: ") + hipGetErrorString(e);
@@ -156,11 +269,14 @@ hipError_t warm_slots(sbf_server *sv) {
     const uint64_t n = 64, back = std::min<uint64_t>(n, (sv->cap_records + 1) * sizeof(uint64_t));
     s.h_off[0] = 0;
     s.h_off[1] = n;
+    s.h_desc[0] = CopyDesc{nullptr, nullptr, 0, n, n};
     e = hipMemsetAsync(s.d_seq, 'A', n, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.d_off, s.h_off, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, s.stream);
-    if (e == hipSuccess && (sbf_mark_record_starts_dev(s.d_off, 1, n, s.d_starts, s.stream) != SBF_OK ||
+    if (e == hipSuccess) e = launch_copy(true, s.dv_desc, 1, (uint8_t *)s.d_seq, s.stream);
+    if (e == hipSuccess && (sbf_mark_record_starts_dev(s.dv_off, 1, n, s.d_starts, s.stream) != SBF_OK ||
                             sbf_query_marked_dev(sv->f, s.d_seq, n, s.d_starts, s.d_out, s.stream) != SBF_OK))
       e = hipErrorLaunchFailure;
+    if (e == hipSuccess) e = launch_copy(false, s.dv_desc, 1, s.d_out, s.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s.h_off, s.d_out, back, hipMemcpyDeviceToHost, s.stream);
     if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
     if (e == hipSuccess) e = hipEventSynchronize(s.done);
@@ -280,11 +396,19 @@ sbf_server *sbf_server_create(sbf_filter *f, uint32_t slots, uint64_t slot_bases
     Slot &s = sv->slots[i];
     e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMalloc((void **)&s.d_seq, slot_bases);
-    if (e == hipSuccess) e = hipMalloc((void **)&s.d_out, slot_bases);
+    // room for up to 15 padding bases per request (a request has >= 1 record)
+    const uint64_t room = slot_bases + 16 * (slot_records + 1);
+    if (e == hipSuccess) e = hipMalloc((void **)&s.d_seq, room);
+    if (e == hipSuccess) e = hipMalloc((void **)&s.d_out, room);
     if (e == hipSuccess) e = hipMalloc((void **)&s.d_off, (slot_records + 1) * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc((void **)&s.d_starts, (slot_bases + 31) / 32 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void **)&s.d_starts, (room + 31) / 32 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_off, (slot_records + 1) * sizeof(uint64_t), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s.h_desc, slot_records * sizeof(CopyDesc), 0);
+    void *dv = nullptr;
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&dv, s.h_off, 0);
+    if (e == hipSuccess) s.dv_off = (const uint64_t *)dv;
+    if (e == hipSuccess) e = hipHostGetDevicePointer(&dv, s.h_desc, 0);
+    if (e == hipSuccess) s.dv_desc = (const CopyDesc *)dv;
     // the filter's per-stream scratch for this slot, allocated now rather
     // than inside the first request
     if (e == hipSuccess && sbf::prepare_stream(f, s.stream) != SBF_OK) e = hipErrorOutOfMemory;
@@ -347,6 +471,8 @@ int sbf_server_submit(sbf_server *sv, const char *seq, const uint64_t *off, uint
   r->nrec = nrec;
   r->out = out;
   r->bases = bases;
+  r->direct_in = bases && device_view(seq);
+  r->direct_out = bases && device_view(out);
   r->t_submit = now_ns();
   {
     std::lock_guard<std::mutex> lk(sv->mu);

@@ -134,3 +134,50 @@ def test_server_admission_and_busy(served):
     want = oracle.query(p, bits, seq.numpy(), [0, 4000])
     for o in outs:
         assert np.array_equal(o.numpy(), want)
+
+
+@pytest.mark.parametrize("window_us", [0, 3000])
+def test_server_mixed_buffer_kinds(served, window_us):
+    """Requests whose buffers the server's copy kernels move (16-byte aligned
+    pinned memory) share batches with requests it copies through the runtime
+    (pageable arrays, pinned views at odd offsets); every answer equals the
+    oracle's, and bytes around each output view stay untouched."""
+    from paper_2606_24417_amd import Server
+
+    f, p, bits, ins, ioff = served
+    reqs = make_requests(ins, ioff, 40, 11, max_reads=200)
+    sv = Server(f, slots=3, slot_bases=1 << 21, slot_records=1 << 12)
+    if window_us:
+        sv.set_batch_window(window_us)
+    jobs = []
+    for i, (seq, off, pin, out) in enumerate(reqs):
+        kind = i % 4
+        n = seq.size
+        if kind == 0:  # aligned pinned in and out
+            s_buf, o_buf, o_view = pin, out, out
+        elif kind == 1:  # pageable in and out
+            s_buf = np.ascontiguousarray(seq)
+            o_buf = np.full(n, 7, dtype=np.uint8)
+            o_view = o_buf
+        elif kind == 2:  # pinned views at odd offsets
+            s_big = torch.zeros(n + 8, dtype=torch.uint8).pin_memory()
+            s_big[3:3 + n] = torch.from_numpy(seq)
+            o_big = torch.full((n + 8,), 9, dtype=torch.uint8).pin_memory()
+            s_buf, o_buf, o_view = s_big[3:3 + n], o_big, o_big[5:5 + n]
+        else:  # aligned pinned in, pageable out
+            s_buf = pin
+            o_buf = np.full(n, 7, dtype=np.uint8)
+            o_view = o_buf
+        jobs.append((i, kind, o_buf, o_view, sv.submit(s_buf, off, o_view), s_buf))
+    for i, kind, o_buf, o_view, t, _ in jobs:
+        sv.wait(t)
+    st = sv.stats()
+    sv.close()
+    assert st["requests"] == len(reqs)
+    for i, kind, o_buf, o_view, t, _ in jobs:
+        seq, off = reqs[i][0], reqs[i][1]
+        got = o_view.numpy() if hasattr(o_view, "numpy") else o_view
+        assert np.array_equal(got, oracle.query(p, bits, seq, off)), "request %d (kind %d)" % (i, kind)
+        if kind == 2:
+            whole = o_buf.numpy()
+            assert (whole[:5] == 9).all() and (whole[5 + seq.size:] == 9).all(), "bytes outside request %d" % i
