@@ -318,9 +318,17 @@ def bench_served(args):
     for t in tk:
         sv.wait(t)
     prev = sv.stats()
+    # The client's own CPU work between rates (refilling and comparing answer
+    # tensors) runs on one thread: OpenMP workers keep spinning after a
+    # parallel region, and with the client's spin loop and the server's
+    # scheduler they can exceed a container's CPU quota, which throttles every
+    # thread of the process, the scheduler included, for milliseconds.
+    torch_threads = torch.get_num_threads()
+    torch.set_num_threads(1)
     for rate in [float(x) for x in args.rates.split(",")]:
         for i in range(len(ref)):
             reqs[i][2].fill_(7)  # answers of this rate only
+        time.sleep(0.2)
         gaps = rng.exponential(1.0 / rate, nreq)
         tickets = []
         start = time.perf_counter()
@@ -348,6 +356,7 @@ def bench_served(args):
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
     sv.close()
+    torch.set_num_threads(torch_threads)
     res = {"metric": "served form: query latency p50/p99 (ms) and k-mers/s under Poisson arrivals",
            "unit": "ms", "higher_is_better": False, "value": rows[0]["p50_ms"], "rates": rows,
            "config": {"workload": "served: %d bp genome resident, %d requests of 1..10000 reads" % (g[0].size, nreq),

@@ -20,6 +20,7 @@
 #include "sbf_internal.h"
 
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -286,6 +287,9 @@ hipError_t warm_slots(sbf_server *sv) {
 }
 
 void scheduler(sbf_server *sv) {
+  // The loop below polls busy slots with 5 us sleeps; Linux's default 50 us
+  // timer slack would stretch each to ~57 us and delay every completion.
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   hipError_t e = hipSetDevice(sv->device);
   if (e == hipSuccess) e = warm_slots(sv);
   {
