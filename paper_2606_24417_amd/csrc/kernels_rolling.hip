@@ -36,6 +36,31 @@ namespace {
 template <int K, int L>
 constexpr int lane_granules() { return (L + K - 1 + 15) / 16 + 1; }
 
+// Bit r: k-mer r of a lane is valid (all its bases are A/C/G/T and no record
+// starts inside it).  The lane's bases start at granule g0 of the staged
+// tile; k-mers 0..31 are judged on the 64 bases from granule g0 on, k-mers
+// 32..L-1 on the 64 bases from granule g0 + 2 on.
+template <int K, int L>
+__device__ __forceinline__ uint64_t lane_kmer_valid(const uint32_t *s_vb, int g0) {
+  static_assert(L % 16 == 0 && L <= 64 && (L <= 32 ? L + K - 1 <= 64 : L + K - 1 <= 96),
+                "k-mer validity comes from one or two 64-base windows");
+  auto window = [&](int g) {
+    uint64_t vbits = 0, sbits = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t vb = s_vb[g0 + g + i];
+      vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
+      sbits |= (uint64_t)(vb >> 16) << (16 * i);
+    }
+    return kmer_valid_mask<K>(vbits, sbits);
+  };
+  if constexpr (L <= 32) {
+    return window(0) & ((1ull << L) - 1);
+  } else {
+    return (window(0) & 0xFFFFFFFFull) | ((window(2) & ((1ull << (L - 32)) - 1)) << 32);
+  }
+}
+
 // Tile scheduler.  A plain launch runs tile blockIdx.x once; a persistent
 // launch (counter not null) keeps taking the next tile index from a device
 // counter (the work queue) until all ntiles are taken.  The decision is
@@ -206,7 +231,6 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
   constexpr int NGW = lane_granules<K, L>();
   constexpr int NGRAN = (WG - 1) * GPL + NGW;
   constexpr int NW = H < 4 ? H : 4;
-  static_assert(L % 16 == 0 && L + K - 1 <= 64, "a lane's bases fit one 64-bit validity word");
   static_assert(Z >= 0 && W >= 1, "s <= k and m <= k");
 
   __shared__ uint32_t s_codes[NGRAN];
@@ -222,17 +246,9 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
 
     const int g0 = threadIdx.x * GPL;
     uint32_t a[NGW];
-    uint64_t vbits = 0, sbits = 0;
 #pragma unroll
-    for (int i = 0; i < NGW; ++i) {
-      a[i] = s_codes[g0 + i];
-      if (i < 4) {
-        const uint32_t vb = s_vb[g0 + i];
-        vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
-        sbits |= (uint64_t)(vb >> 16) << (16 * i);
-      }
-    }
-    const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
+    for (int i = 0; i < NGW; ++i) a[i] = s_codes[g0 + i];
+    const uint64_t kv = lane_kmer_valid<K, L>(s_vb, g0);
 
     uint64_t seg[4] = {0, 0, 0, 0};  // the open segment's masks
     uint32_t cur = 0;                // and its shard
@@ -511,9 +527,12 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
 // kernel.  For k-mer r it forms the OR A(r) of the one-hot masks of its z+1
 // s-mers (the same pair trick), issues the two 16-byte loads of its shard, and
 // D k-mers later tests (A(r) & ~shard) == 0, so the load latency overlaps the
-// hashing of the next k-mers.  Consecutive k-mers of a lane share their shard
-// while they stay in one super-k-mer, so the repeated loads hit the cache.
-// Answers are packed four per register and written as 16-byte stores.
+// hashing of the next k-mers.  A lane loads its own shard only where the shard
+// changes (about once per super-k-mer) and otherwise keeps the previous
+// words.  Lanes walk L = 48 k-mers (three van Herk blocks of 16), which
+// spreads the w-1 extra m-mer hashes, z extra s-mers and the shard load at a
+// lane's start over more k-mers than L = 32.  Answers are kept as one bit per
+// k-mer and spread to bytes for 16-byte stores at the end.
 // ---------------------------------------------------------------------------
 template <int K, int S, int M, int H, int L, int WG, int D>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void query_lane_kernel(const uint8_t *__restrict__ seq, uint64_t len,
@@ -526,7 +545,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
   constexpr int GPL = L / 16;
   constexpr int NGW = lane_granules<K, L>();
   constexpr int NGRAN = (WG - 1) * GPL + NGW;
-  static_assert(L % 16 == 0 && L + K - 1 <= 64, "a lane's bases fit one 64-bit validity word");
   static_assert(D >= 1 && D < L, "test distance");
 
   __shared__ uint32_t s_codes[NGRAN];
@@ -535,7 +553,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
   // slot i holds the suffix minimum i of the current block until step i has
   // used it, then the hash of position i of the next block.  Keeping these 32
   // 64-bit values out of registers lets the kernel run four waves per SIMD
-  // (at most 128 VGPRs; 37 KB of LDS per workgroup, four workgroups per CU).
+  // (at most 128 VGPRs; 38 KB of LDS per workgroup at L = 48, four
+  // workgroups in the 160 KB of a CU).
   __shared__ uint64_t s_vh[W][WG];
 
   __shared__ uint32_t s_next_tile;
@@ -547,27 +566,21 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
 
     const int g0 = threadIdx.x * GPL;
     uint32_t a[NGW];
-    uint64_t vbits = 0, sbits = 0;
 #pragma unroll
-    for (int i = 0; i < NGW; ++i) {
-      a[i] = s_codes[g0 + i];
-      if (i < 4) {
-        const uint32_t vb = s_vb[g0 + i];
-        vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
-        sbits |= (uint64_t)(vb >> 16) << (16 * i);
-      }
-    }
-    const uint64_t kv = kmer_valid_mask<K>(vbits, sbits) & (L == 64 ? ~0ull : ((1ull << L) - 1));
-    const uint64_t pos0 = base + (uint64_t)threadIdx.x * L;
-    uint32_t res[L / 4];
+    for (int i = 0; i < NGW; ++i) a[i] = s_codes[g0 + i];
+    const uint64_t kv = lane_kmer_valid<K, L>(s_vb, g0);
+    // Bit r of ans: k-mer r found (the validity mask is applied at the end).
+    uint32_t ans[(L + 31) / 32];
 #pragma unroll
-    for (int i = 0; i < L / 4; ++i) res[i] = 0;
+    for (int i = 0; i < (L + 31) / 32; ++i) ans[i] = 0;
 
     if (kv != 0) {
       uint64_t oh[L + Z][4];
       uint64_t pr[L + Z][4];
-      uint64_t need[L][4];     // A(r), kept D k-mers
-      uint64_t got[L][4];      // shard of k-mer r, kept D k-mers
+      uint64_t need[L][4];     // A(r), kept D k-mers (z != 3)
+      uint64_t ldw[L][4];      // words loaded for k-mer r (its shard, or shard 0)
+      bool fresh_at[L];        // k-mer r loaded its own shard
+      uint64_t got[4];         // shard words of the last tested k-mer
       uint32_t prev_sh = 0;
 #pragma unroll
       for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
@@ -589,14 +602,29 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
         }
       }
       auto test = [&](int r) {
-        uint32_t miss = 0;
+        // Select the shard words here, D k-mers after the load was issued,
+        // so that the wait for the load does not follow the load at once.
+#pragma unroll
+        for (int w = 0; w < 4; ++w) got[w] = (r == 0 || fresh_at[r]) ? ldw[r][w] : got[w];
+        // Bits of A(r) missing from the shard.  With z = 3, A(r) is the OR of
+        // two pair masks and each 32-bit half of the missing bits is one
+        // three-input operation (a | b) & ~c (truth table 0x54 over the
+        // operand tables 0xF0, 0xCC, 0xAA).
+        uint32_t m[8];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          const uint64_t m = need[r][w] & ~got[r][w];
-          miss |= (uint32_t)m | (uint32_t)(m >> 32);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const uint32_t g = (uint32_t)(got[w] >> (32 * h));
+            if constexpr (Z == 3)
+              m[2 * w + h] = __builtin_amdgcn_bitop3_b32((uint32_t)(pr[r][w] >> (32 * h)),
+                                                         (uint32_t)(pr[r + 2][w] >> (32 * h)), g, 0x54);
+            else
+              m[2 * w + h] = (uint32_t)(need[r][w] >> (32 * h)) & ~g;
+          }
         }
-        const uint32_t present = (miss == 0 && ((kv >> r) & 1ull)) ? 1u : 0u;
-        res[r >> 2] |= present << (8 * (r & 3));
+        const uint32_t miss = (m[0] | m[1] | m[2]) | (m[3] | m[4] | m[5]) | (m[6] | m[7]);
+        if (miss == 0) ans[r >> 5] |= 1u << (r & 31);
       };
 #pragma unroll
       for (int q = 0; q * W < L; ++q) {
@@ -624,16 +652,16 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
             const uint32_t lsh = fresh ? sh : 0u;
             const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)lsh);
             const uint4 lo = p[0], hi = p[1];
-            const uint64_t ld[4] = {((uint64_t)lo.y << 32) | lo.x, ((uint64_t)lo.w << 32) | lo.z,
-                                    ((uint64_t)hi.y << 32) | hi.x, ((uint64_t)hi.w << 32) | hi.z};
-#pragma unroll
-            for (int w = 0; w < 4; ++w) got[r][w] = (r == 0 || fresh) ? ld[w] : got[r > 0 ? r - 1 : 0][w];
+            ldw[r][0] = ((uint64_t)lo.y << 32) | lo.x;
+            ldw[r][1] = ((uint64_t)lo.w << 32) | lo.z;
+            ldw[r][2] = ((uint64_t)hi.y << 32) | hi.x;
+            ldw[r][3] = ((uint64_t)hi.w << 32) | hi.z;
+            fresh_at[r] = fresh;
             smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
             if constexpr (Z == 3) {
 #pragma unroll
               for (int w = 0; w < 4; ++w) {
                 pr[r + 2][w] = oh[r + 2][w] | oh[r + 3][w];
-                need[r][w] = pr[r][w] | pr[r + 2][w];
               }
             } else {
 #pragma unroll
@@ -661,14 +689,25 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
 #pragma unroll
       for (int r = L - D; r < L; ++r) test(r);
     }
-    if (out_aligned16 && pos0 + L <= n_out) {
-      uint4 *o = reinterpret_cast<uint4 *>(out + pos0);
 #pragma unroll
-      for (int i = 0; i < L / 16; ++i) o[i] = make_uint4(res[4 * i], res[4 * i + 1], res[4 * i + 2], res[4 * i + 3]);
+    for (int i = 0; i < (L + 31) / 32; ++i) ans[i] &= (uint32_t)(kv >> (32 * i));
+    // One answer byte per k-mer: four bits x of ans spread to bytes by
+    // x * 0x204081 (x, x<<7, x<<14, x<<21 do not overlap), 16 k-mers per
+    // 16-byte store from a workgroup-uniform base plus a 32-bit lane offset;
+    // byte stores for a lane that ends past n_out or an unaligned output.
+    auto bytes4 = [&](int r) { return (((ans[r >> 5] >> (r & 31)) & 0xFu) * 0x204081u) & 0x01010101u; };
+    uint8_t *const out_tile = out + base;
+    const uint32_t lane_off = (uint32_t)threadIdx.x * (uint32_t)L;
+    if (out_aligned16 && base + lane_off + L <= n_out) {
+#pragma unroll
+      for (int c = 0; c < L / 16; ++c)
+        *reinterpret_cast<uint4 *>(out_tile + lane_off + 16 * c) =
+            make_uint4(bytes4(16 * c), bytes4(16 * c + 4), bytes4(16 * c + 8), bytes4(16 * c + 12));
     } else {
+      const uint64_t pos0 = base + lane_off;
 #pragma unroll
       for (int r = 0; r < L; ++r)
-        if (pos0 + r < n_out) out[pos0 + r] = (uint8_t)(res[r >> 2] >> (8 * (r & 3)));
+        if (pos0 + r < n_out) out[pos0 + r] = (uint8_t)((ans[r >> 5] >> (r & 31)) & 1u);
     }
   }
 }
@@ -676,7 +715,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
 constexpr int kInsertL = 32;
 constexpr int kInsertWG = 256;
 constexpr int kQueryWG = 256;
-constexpr int kQueryLaneL = 32;
+constexpr int kQueryLaneL = 48;
 constexpr int kQueryLaneWG = 256;
 constexpr int kQueryLaneD = 1;
 
