@@ -126,8 +126,13 @@ __device__ __forceinline__ void smer_onehots(uint64_t g, uint64_t (&oh)[4]) {
 // kAtomic (the paper's four atomicOr per run head).
 enum InsertMode : int { kAtomic = 0, kStore = 1, kRepair = 2 };
 
-constexpr int kQueueSlots = 3;  // finished segments a lane buffers in LDS
-constexpr int kSubRun = 8;      // k-mers between two drains of the buffer
+// A lane buffers finished segments in LDS and applies them every kSubRun
+// k-mers (and at the end), loading all buffered shards before the first
+// store, so one wait covers several read-modify-writes; a segment that finds
+// the buffer full is applied with atomics at once.  With a mean super-k-mer
+// of about 8.5 k-mers, a drain every 12 k-mers finds 1.4 segments on average.
+constexpr int kQueueSlots = 3;
+constexpr int kSubRun = 12;
 
 template <int NW>
 __device__ __forceinline__ void atomic_segment(uint64_t *__restrict__ words, uint32_t shard, const uint64_t (&m)[4]) {
