@@ -125,13 +125,42 @@ def test_tiny_workload(variant, path):
     assert ans[:n_pos].sum() == n_pos  # no false negatives
 
 
-@pytest.mark.parametrize("n", [0, 1, 30, 31, 32, 33, 64, 4126, 4127, 4128, 8222, 8223, 8224, 12345, 50_000])
+# Lengths at k-mer counts around one lane of the lane query (48 k-mers), the
+# two-phase query tile (4096), the insert tile (8192) and one and two lane
+# query tiles (12288, 24576): n = k-mers + 30.
+@pytest.mark.parametrize("n", [0, 1, 30, 31, 32, 33, 64, 77, 78, 79, 4126, 4127, 4128, 8222, 8223, 8224, 12345,
+                               12317, 12318, 12319, 24605, 24606, 24607, 50_000])
 def test_lengths_around_tiles(n):
     rng = np.random.default_rng(n)
     seq = noisy(rng, n, 0.002, 0.1)
     print("case length", n, flush=True)
     for variant in ("rolling", "generic"):
         check(HOT + (1 << 14,), [(seq, None)], (seq, None), variant=variant)
+
+
+# Base offsets, relative to the first base of a lane, where an invalid base
+# or a record start decides k-mer validity across the seam between a lane's
+# two 64-base validity windows (k-mers 0..31 judged on bases 0..63, k-mers
+# 32..47 on bases 32..95: an invalid base at 61 ends k-mer 31, at 62 only
+# k-mers from 32 on) and where lanes of 32 or 48 k-mers end.
+SEAM_OFFSETS = [1, 30, 31, 32, 33, 47, 48, 61, 62, 63, 64, 77, 78]
+
+
+@pytest.mark.parametrize("lane", [32, 48])
+def test_validity_at_lane_window_seams(lane):
+    """One invalid base in every fourth lane and one record start in every
+    fourth lane (another phase), each at a seam offset, cycling through them."""
+    rng = np.random.default_rng(700 + lane)
+    n = 200_000
+    seq = noisy(rng, n, 0.0, 0.05)
+    nl = n // lane - 2
+    for j, li in enumerate(range(0, nl, 4)):
+        seq[li * lane + SEAM_OFFSETS[j % len(SEAM_OFFSETS)]] = ord("N")
+    starts = sorted({li * lane + SEAM_OFFSETS[j % len(SEAM_OFFSETS)] for j, li in enumerate(range(2, nl, 4))})
+    off = np.array([0] + starts + [n], dtype=np.uint64)
+    print("case seams", lane, flush=True)
+    _, ans = check(HOT + (1 << 24,), [(seq, off)], (seq, off))
+    assert ans.sum() > n // 2  # most k-mers stay valid, so the seams decide
 
 
 @pytest.mark.parametrize("bits", [1, 256, 257, 4096, 1 << 20, 1 << 30])
