@@ -117,14 +117,17 @@ __device__ __forceinline__ void smer_onehots(uint64_t g, uint64_t (&oh)[4]) {
 // How a finished segment reaches the filter.  Global atomics on this GPU run
 // at a fixed ~27 G ops/s whatever the filter size, while plain random 32-byte
 // read-modify-writes run several times faster, so the default insert is two
-// passes over the same segments:
+// passes over the same k-mers:
 //   kStore:  read the shard, OR the segment's masks, write it back (plain
 //            accesses; a read-modify-write racing with another one on the
 //            same shard can lose that one's bits, never older bits);
-//   kRepair: read the shard and atomically OR only the bits still missing.
+//   repair:  the lane query walk (query_lane_kernel with REPAIR) tests every
+//            valid k-mer against its shard and atomically ORs the bits still
+//            missing (a few percent of the segments in cache, fewer out of
+//            cache).
 // After both passes the filter is exactly the OR of every segment, as with
 // kAtomic (the paper's four atomicOr per run head).
-enum InsertMode : int { kAtomic = 0, kStore = 1, kRepair = 2 };
+enum InsertMode : int { kAtomic = 0, kStore = 1 };
 
 // A lane buffers finished segments in LDS and applies them every kSubRun
 // k-mers (and at the end), loading all buffered shards before the first
@@ -163,8 +166,7 @@ __device__ __forceinline__ void push_segment(SegmentBuffer<WG> &b, int &n, uint6
   ++n;
 }
 
-// Apply the buffered segments: all loads first, then the stores (kStore) or
-// the atomic repairs (kRepair).
+// Apply the buffered segments: all loads first, then the stores.
 template <int NW, int MODE, int WG>
 __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uint64_t *__restrict__ words) {
   if constexpr (MODE != kAtomic) {
@@ -185,38 +187,24 @@ __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uin
         old[k][3] = ((uint64_t)hi.w << 32) | hi.z;
       }
     }
-    if constexpr (MODE == kStore) {
-      // a later buffered segment on the same shard carries the earlier masks,
-      // since its read does not see the earlier write of this lane
+    // a later buffered segment on the same shard carries the earlier masks,
+    // since its read does not see the earlier write of this lane
 #pragma unroll
-      for (int k = 1; k < kQueueSlots; ++k)
+    for (int k = 1; k < kQueueSlots; ++k)
 #pragma unroll
-        for (int j = 0; j < k; ++j)
-          if (k < n && sh[k] == sh[j])
+      for (int j = 0; j < k; ++j)
+        if (k < n && sh[k] == sh[j])
 #pragma unroll
-            for (int w = 0; w < 4; ++w) m[k][w] |= m[j][w];
+          for (int w = 0; w < 4; ++w) m[k][w] |= m[j][w];
 #pragma unroll
-      for (int k = 0; k < kQueueSlots; ++k) {
-        if (k < n) {
-          uint64_t v[4];
+    for (int k = 0; k < kQueueSlots; ++k) {
+      if (k < n) {
+        uint64_t v[4];
 #pragma unroll
-          for (int w = 0; w < 4; ++w) v[w] = old[k][w] | m[k][w];
-          uint4 *p = reinterpret_cast<uint4 *>(words + 4ull * (uint64_t)sh[k]);
-          p[0] = make_uint4((uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32));
-          p[1] = make_uint4((uint32_t)v[2], (uint32_t)(v[2] >> 32), (uint32_t)v[3], (uint32_t)(v[3] >> 32));
-        }
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < kQueueSlots; ++k) {
-        if (k < n) {
-          uint64_t *p = words + 4ull * (uint64_t)sh[k];
-#pragma unroll
-          for (int w = 0; w < NW; ++w) {
-            const uint64_t miss = m[k][w] & ~old[k][w];
-            if (miss) atomic_or64(p + w, miss);
-          }
-        }
+        for (int w = 0; w < 4; ++w) v[w] = old[k][w] | m[k][w];
+        uint4 *p = reinterpret_cast<uint4 *>(words + 4ull * (uint64_t)sh[k]);
+        p[0] = make_uint4((uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32));
+        p[1] = make_uint4((uint32_t)v[2], (uint32_t)(v[2] >> 32), (uint32_t)v[3], (uint32_t)(v[3] >> 32));
       }
     }
     n = 0;
@@ -539,10 +527,11 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
 // lane's start over more k-mers than L = 32.  Answers are kept as one bit per
 // k-mer and spread to bytes for 16-byte stores at the end.
 // ---------------------------------------------------------------------------
-template <int K, int S, int M, int H, int L, int WG, int D>
+template <int K, int S, int M, int H, int L, int WG, int D, bool REPAIR = false>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void query_lane_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                         const uint32_t *__restrict__ starts, int aligned16,
-                                                        const uint64_t *__restrict__ words, uint32_t shard_mask,
+                                                        typename std::conditional<REPAIR, uint64_t, const uint64_t>::type *words,
+                                                        uint32_t shard_mask,
                                                         uint8_t *__restrict__ out, uint64_t n_out,
                                                         int out_aligned16, TileQueue tq) {
   constexpr int W = K - M + 1;
@@ -585,6 +574,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
       uint64_t need[L][4];     // A(r), kept D k-mers (z != 3)
       uint64_t ldw[L][4];      // words loaded for k-mer r (its shard, or shard 0)
       bool fresh_at[L];        // k-mer r loaded its own shard
+      uint32_t sh_at[L];       // shard of k-mer r (repair)
       uint64_t got[4];         // shard words of the last tested k-mer
       uint32_t prev_sh = 0;
 #pragma unroll
@@ -629,7 +619,22 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
           }
         }
         const uint32_t miss = (m[0] | m[1] | m[2]) | (m[3] | m[4] | m[5]) | (m[6] | m[7]);
-        if (miss == 0) ans[r >> 5] |= 1u << (r & 31);
+        if constexpr (REPAIR) {
+          // Insert repair: OR the missing bits of a valid k-mer into its
+          // shard and into the cached words, so that later k-mers of the run
+          // do not repeat them.
+          if (miss != 0 && ((kv >> r) & 1ull)) {
+            uint64_t *p = words + 4ull * (uint64_t)sh_at[r];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              const uint64_t mw = ((uint64_t)m[2 * w + 1] << 32) | m[2 * w];
+              if (mw) atomic_or64(p + w, mw);
+              got[w] |= mw;
+            }
+          }
+        } else {
+          if (miss == 0) ans[r >> 5] |= 1u << (r & 31);
+        }
       };
 #pragma unroll
       for (int q = 0; q * W < L; ++q) {
@@ -662,6 +667,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
             ldw[r][2] = ((uint64_t)hi.y << 32) | hi.x;
             ldw[r][3] = ((uint64_t)hi.w << 32) | hi.z;
             fresh_at[r] = fresh;
+            sh_at[r] = sh;
             smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
             if constexpr (Z == 3) {
 #pragma unroll
@@ -694,6 +700,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
 #pragma unroll
       for (int r = L - D; r < L; ++r) test(r);
     }
+    if constexpr (REPAIR) continue;  // no answers
 #pragma unroll
     for (int i = 0; i < (L + 31) / 32; ++i) ans[i] &= (uint32_t)(kv >> (32 * i));
     // One answer byte per k-mer: four bits x of ans spread to bytes by
@@ -765,8 +772,11 @@ hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a
   }
   SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kStore>), kInsertWG, ntiles, 0, a.seq,
                    a.len, a.starts, aligned, words, shard_mask);
-  SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kRepair>), kInsertWG, ntiles, 1, a.seq,
-                   a.len, a.starts, aligned, words, shard_mask);
+  // Repair pass: the lane query walk, OR-ing the bits the store pass lost.
+  const uint64_t qtile = (uint64_t)kQueryLaneL * kQueryLaneWG;
+  SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, kQueryLaneL, kQueryLaneWG, kQueryLaneD, true>), kQueryLaneWG,
+                   (nk + qtile - 1) / qtile, 1, a.seq, a.len, a.starts, aligned, words, shard_mask,
+                   (uint8_t *)nullptr, nk, 0);
   return hipSuccess;
 }
 
