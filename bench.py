@@ -739,8 +739,8 @@ def main():
     roof_q = roofline("query", q_mean, n_q_kmers, 1)
     roof_q["kernel"] = q_kernel
     roof_i = roofline("insert", i_mean, n_ins_kmers, ins_launches)
-    roof_i["kernel"] = "insert_rolling_kernel<31,28,16,4> (%s)" % (
-        "store + repair passes" if ins_launches == 2 else "atomic")
+    roof_i["kernel"] = ("insert_rolling_kernel<31,28,16,4> store pass + query_lane_kernel<31,28,16,4> repair walk"
+                        if ins_launches == 2 else "insert_rolling_kernel<31,28,16,4> (atomic)")
     if q_mean >= i_mean / ins_launches:
         roof, roof_other = roof_q, roof_i
     else:
