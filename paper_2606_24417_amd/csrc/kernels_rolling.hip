@@ -167,7 +167,7 @@ __device__ __forceinline__ void push_segment(SegmentBuffer<WG> &b, int &n, uint6
 }
 
 // Apply the buffered segments: all loads first, then the stores.
-template <int NW, int MODE, int WG>
+template <int MODE, int WG>
 __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uint64_t *__restrict__ words) {
   if constexpr (MODE != kAtomic) {
     const int t = threadIdx.x;
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
             for (int w = 0; w < 4; ++w) seg[w] = (seg[w] & keep) | A[w];
             open = v;
             cur = sh;
-            if (r % kSubRun == kSubRun - 1 && r + 1 < L) drain_segments<NW, MODE>(s_buf, nbuf, words);
+            if (r % kSubRun == kSubRun - 1 && r + 1 < L) drain_segments<MODE>(s_buf, nbuf, words);
           }
         }
         if ((q + 1) * W < L) {
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
     const bool absorbed = __shfl_up((int)absorb, 1, 64) != 0 && lane > 0;
     if (held && !absorbed) push_segment<NW, MODE>(s_buf, nbuf, words, fsh, fseg);
     if (open) push_segment<NW, MODE>(s_buf, nbuf, words, cur, seg);
-    drain_segments<NW, MODE>(s_buf, nbuf, words);
+    drain_segments<MODE>(s_buf, nbuf, words);
   }
 }
 
