@@ -178,6 +178,50 @@ def run_probes(sizes_mib, copy_only=False, modes=None, quiet=False):
     return out
 
 
+VALU_OPS = ["add32", "mul32", "mad64", "shl64", "bitop3", "cmp64"]
+SBF_PROBE_VALU_ADD32 = 0
+
+
+def valu_rate(op):
+    """Wave-level instructions per second of VALU probe `op` (include/sbf_probe.h)."""
+    import ctypes
+
+    from paper_2606_24417_amd import build
+
+    L = ctypes.CDLL(build.PROBE_LIB)
+    fn = L.sbf_probe_valu
+    fn.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    rc = fn(op, ctypes.byref(rate), ctypes.byref(ms))
+    if rc != 0:
+        raise SystemExit("VALU probe failed rc=%d (op %d)" % (rc, op))
+    return rate.value
+
+
+def run_valu_probes():
+    """Integer VALU issue rates from libsbf_probe.so (include/sbf_probe.h),
+    as wave-level instructions per second and as a fraction of one wave64
+    instruction per SIMD every four cycles at 2.4 GHz (256 CUs)."""
+    import ctypes
+
+    from paper_2606_24417_amd import build
+
+    L = ctypes.CDLL(build.PROBE_LIB)
+    fn = L.sbf_probe_valu
+    fn.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    full = 256 * 4 * 2.4e9 / 4
+    row = {"one_per_4_cycles_G_wave_instr_per_s": round(full / 1e9, 1)}
+    for op, name in enumerate(VALU_OPS):
+        rate, ms = ctypes.c_double(), ctypes.c_double()
+        rc = fn(op, ctypes.byref(rate), ctypes.byref(ms))
+        if rc != 0:
+            raise SystemExit("VALU probe failed rc=%d (op %s)" % (rc, name))
+        row[name] = {"G_wave_instr_per_s": round(rate.value / 1e9, 1), "of_one_per_4_cycles": round(rate.value / full, 3),
+                     "ms": round(ms.value, 3)}
+    print(json.dumps(row), flush=True)
+    return row
+
+
 def bench_batched(args):
     """Batched form: the whole insert batch and query batch in one persistent
     launch each, captured in a HIP graph, against the plain per-batch launch
@@ -568,7 +612,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="served: server execution slots")
     ap.add_argument("--window-us", type=int, default=0, help="served: batching window in microseconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-probe", action="store_true", help="out_of_cache: skip the random-access probe")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the live roofline probes (random access out of cache, 32-bit add rate in cache)")
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")
     ap.add_argument("--bits", type=int, default=0, help="filter size override (default: the workload's)")
     ap.add_argument("--query-mode", type=int, default=0, help="0 lane-sequential, 1 leader load + broadcast, 2 every lane loads")
@@ -577,7 +622,9 @@ def main():
                     help="persistent workgroups per CU for insert,query (0 = one workgroup per tile; "
                          "default: the library's)")
     ap.add_argument("--autotune", action="store_true", help="run the library autotuner on the workload first")
-    ap.add_argument("--probe", action="store_true", help="print random-access and copy roofline probes, then exit")
+    ap.add_argument("--probe", action="store_true",
+                    help="print random-access, copy and integer VALU roofline probes, then exit")
+    ap.add_argument("--probe-valu", action="store_true", help="print the integer VALU issue-rate probes, then exit")
     ap.add_argument("--probe-read-mib", type=int, default=0,
                     help="run only the random 32-byte read probe on a buffer of this many MiB (counter calibration)")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
@@ -590,6 +637,10 @@ def main():
 
     if args.probe:
         run_probes([2, 32, 256, 1024, 8192])
+        run_valu_probes()
+        return
+    if args.probe_valu:
+        run_valu_probes()
         return
     if args.probe_copy_mib:
         run_probes([args.probe_copy_mib], copy_only=True)
@@ -718,6 +769,12 @@ def main():
                 r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "segments": nseg}
         r["traffic"] = counter_traffic(args.workload, part, kmers)
+        if in_cache and valu is not None:
+            # the same algorithmic ops against the 32-bit add rate measured now
+            # on this GPU (simple 32-bit ops issue faster than one wave64
+            # instruction per four cycles on gfx950, so this rate exceeds the
+            # unit-count peak)
+            r["valu_probe"] = {"add32_T_lane_ops_per_s": valu, "frac": round(r["achieved"] / valu, 4)}
         if probe is not None and r.get("segments"):
             # segments (one random 32-byte shard access each) per second against
             # the probe's random read rate (query) or read-modify-write rate (insert)
@@ -729,6 +786,9 @@ def main():
         r["kernel_ms"] = round(ms, 4)
         return r
 
+    valu = None
+    if in_cache and not args.no_probe:
+        valu = round(valu_rate(SBF_PROBE_VALU_ADD32) * 64 / 1e12, 2)
     probe = None
     if not in_cache and not args.no_probe:
         # random 32-byte sector rates over an 8 GiB buffer, measured now on this GPU

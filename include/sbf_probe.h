@@ -1,6 +1,6 @@
 /*
- * sbf_probe.h - micro-benchmarks that set the memory rooflines of the SBF
- * kernels on the current GPU (library libsbf_probe.so).
+ * sbf_probe.h - micro-benchmarks that set the memory and integer-ALU
+ * rooflines of the SBF kernels on the current GPU (library libsbf_probe.so).
  *
  * The insert and query kernels touch one 32-byte shard per super-k-mer
  * segment at a random place in the filter (Section "Data Layout": 256-bit
@@ -34,6 +34,25 @@ extern "C" {
  * error.  Each measurement is the mean of three launches after one warm-up
  * launch. */
 int sbf_probe_random_access(uint64_t bytes, int mode, uint64_t ops, double *per_second, double *ms);
+
+/* Integer vector-ALU issue rates behind the in-cache roofline (Section
+ * "Speed-of-Light Analysis": in cache the kernels are compute-bound).  Each
+ * probe runs one instruction kind in eight independent chains per lane over
+ * a grid of 8192 waves; the instructions are those the hashing, sliding
+ * minimum and mask tests of the kernels compile to. */
+#define SBF_PROBE_VALU_ADD32 0   /* v_add_u32: 32-bit add */
+#define SBF_PROBE_VALU_MUL32 1   /* v_mul_lo_u32: low half of a 32x32-bit product */
+#define SBF_PROBE_VALU_MAD64 2   /* v_mad_u64_u32: 32x32-bit product plus a 64-bit addend */
+#define SBF_PROBE_VALU_SHL64 3   /* v_lshlrev_b64: 64-bit shift */
+#define SBF_PROBE_VALU_BITOP3 4  /* v_bitop3_b32: three-input bitwise function */
+#define SBF_PROBE_VALU_CMP64 5   /* v_cmp_lt_u64: 64-bit compare into a lane mask */
+
+/* Run VALU probe `op` on the current device.  On success writes the rate in
+ * wave-level instructions per second to *wave_instr_per_second and the mean
+ * kernel time to *ms and returns 0; -1 for a bad op, -2 when a small device
+ * allocation fails, -3 on a HIP error.  Mean of three launches after one
+ * warm-up launch. */
+int sbf_probe_valu(int op, double *wave_instr_per_second, double *ms);
 
 #ifdef __cplusplus
 }

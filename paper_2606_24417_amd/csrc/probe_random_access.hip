@@ -1,4 +1,4 @@
-// Random shard-access and streaming-copy probes (include/sbf_probe.h).
+// Random shard-access, streaming-copy and integer VALU probes (include/sbf_probe.h).
 #include "sbf_probe.h"
 
 #include <hip/hip_runtime.h>
@@ -82,7 +82,90 @@ hipError_t launch(int mode, uint64_t *buf, uint64_t bytes, uint64_t ops, uint64_
   return hipGetLastError();
 }
 
+// Integer VALU issue-rate probe: eight independent chains of one instruction
+// kind per lane, written as inline assembly so that the compiler neither
+// folds nor substitutes them.
+constexpr int kValuBlocks = 2048;   // 8192 waves: eight per SIMD on 256 CUs
+constexpr uint32_t kValuIters = 32768;
+
+template <int OP>
+__global__ __launch_bounds__(kBlock) void valu_chains(uint32_t iters, uint64_t *__restrict__ sink) {
+  uint32_t a[8];
+  uint64_t d[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    a[j] = threadIdx.x * (uint32_t)(2 * j + 1) + blockIdx.x;
+    d[j] = ((uint64_t)a[j] << 32) | (a[j] ^ 0x5bd1e995u);
+  }
+  const uint32_t c = 0x9E3779B9u + (blockIdx.x & 1u);
+  const uint32_t sh = 3u + (threadIdx.x & 1u);
+  uint64_t q[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // scalar results, one register pair per chain
+  for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if constexpr (OP == SBF_PROBE_VALU_ADD32) {
+        asm volatile("v_add_u32_e32 %0, %1, %0" : "+v"(a[j]) : "v"(c));
+      } else if constexpr (OP == SBF_PROBE_VALU_MUL32) {
+        asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(a[j]) : "v"(c));
+      } else if constexpr (OP == SBF_PROBE_VALU_MAD64) {
+        asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(d[j]), "=s"(q[j]) : "v"(a[j]), "v"(c));
+      } else if constexpr (OP == SBF_PROBE_VALU_SHL64) {
+        asm volatile("v_lshlrev_b64 %0, %1, %0" : "+v"(d[j]) : "v"(sh));
+      } else if constexpr (OP == SBF_PROBE_VALU_BITOP3) {
+        asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a[j]) : "v"(c), "v"(sh));
+      } else {
+        asm volatile("v_cmp_lt_u64_e64 %0, %1, %2" : "=s"(q[j]) : "v"(d[j]), "v"(d[(j + 1) & 7]));
+      }
+    }
+  }
+  uint64_t x = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) x ^= d[j] ^ a[j] ^ q[j];
+  if (x == 0x5bd1e9955bd1e995ull) sink[0] = x;  // keeps the chains' results live
+}
+
+hipError_t launch_valu(int op, uint64_t *sink) {
+  const dim3 grid(kValuBlocks), block(kBlock);
+  switch (op) {
+    case SBF_PROBE_VALU_ADD32: hipLaunchKernelGGL(valu_chains<SBF_PROBE_VALU_ADD32>, grid, block, 0, 0, kValuIters, sink); break;
+    case SBF_PROBE_VALU_MUL32: hipLaunchKernelGGL(valu_chains<SBF_PROBE_VALU_MUL32>, grid, block, 0, 0, kValuIters, sink); break;
+    case SBF_PROBE_VALU_MAD64: hipLaunchKernelGGL(valu_chains<SBF_PROBE_VALU_MAD64>, grid, block, 0, 0, kValuIters, sink); break;
+    case SBF_PROBE_VALU_SHL64: hipLaunchKernelGGL(valu_chains<SBF_PROBE_VALU_SHL64>, grid, block, 0, 0, kValuIters, sink); break;
+    case SBF_PROBE_VALU_BITOP3: hipLaunchKernelGGL(valu_chains<SBF_PROBE_VALU_BITOP3>, grid, block, 0, 0, kValuIters, sink); break;
+    default: hipLaunchKernelGGL(valu_chains<SBF_PROBE_VALU_CMP64>, grid, block, 0, 0, kValuIters, sink); break;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+extern "C" int sbf_probe_valu(int op, double *wave_instr_per_second, double *ms) {
+  if (!wave_instr_per_second || !ms || op < SBF_PROBE_VALU_ADD32 || op > SBF_PROBE_VALU_CMP64) return -1;
+  uint64_t *sink = nullptr;
+  if (hipMalloc((void **)&sink, 64) != hipSuccess) return -2;
+  int rc = 0;
+  hipEvent_t a = nullptr, b = nullptr;
+  float t = 0.f;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess || launch_valu(op, sink) != hipSuccess ||
+      hipEventRecord(a, 0) != hipSuccess) {
+    rc = -3;
+  } else {
+    for (int r = 0; r < 3 && rc == 0; ++r)
+      if (launch_valu(op, sink) != hipSuccess) rc = -3;
+    if (rc == 0 && (hipEventRecord(b, 0) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                    hipEventElapsedTime(&t, a, b) != hipSuccess))
+      rc = -3;
+  }
+  if (rc == 0) {
+    *ms = t / 3.0;
+    const double waves = (double)kValuBlocks * (kBlock / 64);
+    *wave_instr_per_second = waves * 8.0 * kValuIters / (*ms * 1e-3);
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(sink);
+  return rc;
+}
 
 extern "C" int sbf_probe_random_access(uint64_t bytes, int mode, uint64_t ops, double *per_second, double *ms) {
   if (!per_second || !ms || mode < SBF_PROBE_READ32 || mode > SBF_PROBE_COPY) return -1;

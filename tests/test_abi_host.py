@@ -101,9 +101,15 @@ def test_probe_library_exports_its_header():
         pytest.skip("libsbf_probe.so not built")
     L = ctypes.CDLL(build.PROBE_LIB)
     names = header_functions(PROBE_HEADER)
-    assert names == ["sbf_probe_random_access"]
+    assert names == ["sbf_probe_random_access", "sbf_probe_valu"]
     for n in names:
         assert hasattr(L, n)
+    v = L.sbf_probe_valu
+    v.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    c, d = ctypes.c_double(), ctypes.c_double()
+    assert v(6, ctypes.byref(c), ctypes.byref(d)) == -1  # bad op
+    assert v(-1, ctypes.byref(c), ctypes.byref(d)) == -1
+    assert v(0, None, None) == -1
     # argument checks happen before any device call
     fn = L.sbf_probe_random_access
     fn.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
