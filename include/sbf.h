@@ -283,12 +283,16 @@ void sbf_server_destroy(sbf_server *sv);
 
 /* Bytes of sequence per chunk of the host entry points (default 64 MiB; at
  * least 4096).  Inputs longer than this are processed in chunks that overlap
- * by k-1 bases, pipelined over two HIP streams: while one chunk's kernel runs,
- * the next chunk is copied into pinned host memory and sent to the device,
- * and the previous chunk's answers come back.  A caller buffer that is
- * already pinned (hipHostMalloc, torch pin_memory) is copied from or to
- * directly.  The library holds up to two chunks of device and pinned host
- * memory (twice that for queries) until the filter is destroyed. */
+ * by k-1 bases, pipelined over two HIP streams: while one chunk's kernel
+ * runs, the next chunk is copied into pinned host memory and sent to the
+ * device, and the previous chunk's answers come back.  With the lane query
+ * (SBF_QUERY_LANE, the default) answers cross the host link as one bit per
+ * k-mer and are spread to bytes on the host (the k-mer starts per chunk are
+ * then rounded down to a multiple of 64).  A caller buffer that is already
+ * pinned (hipHostMalloc, torch pin_memory) is copied from directly, and for
+ * byte answers copied to directly.  The library holds up to two chunks of
+ * device and pinned host memory (plus the answers for queries) until the
+ * filter is destroyed. */
 int sbf_set_staging_bytes(sbf_filter *f, uint64_t bytes);
 
 #ifdef __cplusplus

@@ -224,6 +224,7 @@ hipError_t launch_insert_generic(const Geometry &g, uint64_t *words, const SeqAr
 }
 
 hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st) {
+  if (a.packed) return hipErrorInvalidValue;  // answers as bits come from the lane query only
   switch (g.shard_words) {
     case 4: return launch_generic_query_sw<4>(g, words, a, st);
     case 8: return launch_generic_query_sw<8>(g, words, a, st);

@@ -533,13 +533,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
                                                         typename std::conditional<REPAIR, uint64_t, const uint64_t>::type *words,
                                                         uint32_t shard_mask,
                                                         uint8_t *__restrict__ out, uint64_t n_out,
-                                                        int out_aligned16, TileQueue tq) {
+                                                        int out_aligned16, int out_packed, TileQueue tq) {
   constexpr int W = K - M + 1;
   constexpr int Z = K - S;
   constexpr int GPL = L / 16;
   constexpr int NGW = lane_granules<K, L>();
   constexpr int NGRAN = (WG - 1) * GPL + NGW;
   static_assert(D >= 1 && D < L, "test distance");
+  static_assert(L % 16 == 0 && L <= 64, "a lane's answer bits are whole 16-bit words of one 64-bit value");
 
   __shared__ uint32_t s_codes[NGRAN];
   __shared__ uint32_t s_vb[NGRAN];
@@ -703,6 +704,26 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
     if constexpr (REPAIR) continue;  // no answers
 #pragma unroll
     for (int i = 0; i < (L + 31) / 32; ++i) ans[i] &= (uint32_t)(kv >> (32 * i));
+    if (out_packed) {
+      // One answer bit per k-mer: the lane's L bits start at bit base +
+      // lane_off, a multiple of 16, so they are L/16 aligned 16-bit words;
+      // bits at or past n_out are cleared and bytes past them not written.
+      const uint64_t pos0 = base + (uint64_t)threadIdx.x * L;
+      if (pos0 < n_out) {
+        uint64_t bits = ans[0];
+        if constexpr (L > 32) bits |= (uint64_t)ans[(L + 31) / 32 - 1] << 32;
+        const uint64_t left = n_out - pos0;
+        if (left < (uint64_t)L) bits &= (1ull << left) - 1;
+        uint8_t *ob = out + pos0 / 8;
+        if (left >= (uint64_t)L) {
+#pragma unroll
+          for (int c = 0; c < L / 16; ++c) reinterpret_cast<uint16_t *>(ob)[c] = (uint16_t)(bits >> (16 * c));
+        } else {
+          for (uint64_t j = 0; j < (left + 7) / 8; ++j) ob[j] = (uint8_t)(bits >> (8 * j));
+        }
+      }
+      continue;
+    }
     // One answer byte per k-mer: four bits x of ans spread to bytes by
     // x * 0x204081 (x, x<<7, x<<14, x<<21 do not overlap), 16 k-mers per
     // 16-byte store from a workgroup-uniform base plus a 32-bit lane offset;
@@ -776,7 +797,7 @@ hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a
   const uint64_t qtile = (uint64_t)kQueryLaneL * kQueryLaneWG;
   SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, kQueryLaneL, kQueryLaneWG, kQueryLaneD, true>), kQueryLaneWG,
                    (nk + qtile - 1) / qtile, 1, a.seq, a.len, a.starts, aligned, words, shard_mask,
-                   (uint8_t *)nullptr, nk, 0);
+                   (uint8_t *)nullptr, nk, 0, 0);
   return hipSuccess;
 }
 
@@ -789,9 +810,10 @@ hipError_t query_rolling(const uint64_t *words, uint32_t shard_mask, const SeqAr
     const uint64_t tile = (uint64_t)kQueryLaneL * kQueryLaneWG;
     SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, kQueryLaneL, kQueryLaneWG, kQueryLaneD>), kQueryLaneWG,
                      (a.n_out + tile - 1) / tile, 2, a.seq, a.len, a.starts, aligned, words, shard_mask, a.out,
-                     a.n_out, (int)(((uintptr_t)a.out & 15u) == 0));
+                     a.n_out, (int)(((uintptr_t)a.out & 15u) == 0), a.packed);
     return hipSuccess;
   }
+  if (a.packed) return hipErrorInvalidValue;  // bits only from the lane organisation
   const uint64_t tile = 16ull * kQueryWG;
   if (mode == kQueryLeaderMode)
     SBF_LAUNCH_TILES((query_rolling_kernel<K, S, M, H, kQueryWG, true>), kQueryWG, (a.n_out + tile - 1) / tile, 2,

@@ -80,8 +80,9 @@ struct Pinned {
 };
 
 // One stage of the host pipeline: a stream with the device and pinned host
-// buffers of one chunk.  Two stages alternate, so that the host-side copy and
-// the transfers of one chunk overlap the kernel of the other.
+// buffers of one chunk.  Two stages alternate, so that the host-side copy or
+// answer unpacking of one chunk overlaps the transfers and kernel of the
+// other.
 struct PipeSlot {
   hipStream_t stream = nullptr;
   hipEvent_t kernel_done = nullptr;  // the stage's last kernel has finished
@@ -89,7 +90,8 @@ struct PipeSlot {
   Scratch d_seq, d_out, d_off;
   Pinned h_seq, h_out, h_off;
   uint8_t *flush_dst = nullptr;  // caller buffer for the answers waiting in h_out
-  uint64_t flush_len = 0;
+  uint64_t flush_len = 0;        // answers (bytes in the caller's buffer)
+  bool flush_packed = false;     // h_out holds them as bits
   bool pending = false;
 };
 constexpr int kPipeSlots = 2;
@@ -212,10 +214,14 @@ int run_insert(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::Launc
   return SBF_OK;
 }
 
+int query_kernel_mode(const sbf_filter *f) {
+  return f->query_mode == SBF_QUERY_DIRECT   ? sbf::kQueryDirectMode
+         : f->query_mode == SBF_QUERY_LEADER ? sbf::kQueryLeaderMode
+                                             : sbf::kQueryLaneMode;
+}
+
 int run_query(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::LaunchShape *given = nullptr) {
-  const int mode = f->query_mode == SBF_QUERY_DIRECT   ? sbf::kQueryDirectMode
-                   : f->query_mode == SBF_QUERY_LEADER ? sbf::kQueryLeaderMode
-                                                       : sbf::kQueryLaneMode;
+  const int mode = query_kernel_mode(f);
   hipError_t e;
   if (use_rolling(f)) {
     sbf::LaunchShape ls;
@@ -339,14 +345,64 @@ void host_copy(void *dst, const void *src, size_t n) {
   for (auto &t : th) t.join();
 }
 
+// Byte b of table entry x is bit b of x: one answer byte per answer bit.
+struct BitBytes {
+  uint64_t v[256];
+  BitBytes() {
+    for (int x = 0; x < 256; ++x) {
+      uint64_t e = 0;
+      for (int b = 0; b < 8; ++b) e |= (uint64_t)((x >> b) & 1) << (8 * b);
+      v[x] = e;
+    }
+  }
+};
+const BitBytes kBitBytes;
+
+void unpack_range(uint8_t *dst, const uint8_t *bits, size_t a, size_t b) {
+  // a is a multiple of 8
+  size_t i = a;
+  for (; i + 8 <= b; i += 8) memcpy(dst + i, &kBitBytes.v[bits[i / 8]], 8);
+  for (; i < b; ++i) dst[i] = (uint8_t)((bits[i / 8] >> (i % 8)) & 1u);
+}
+
+// Answer bytes dst[0, n) from answer bits (bit i%8 of bits[i/8]), split over
+// up to 8 host threads for large chunks like host_copy.
+void unpack_bits(uint8_t *dst, const uint8_t *bits, size_t n) {
+  constexpr size_t kPerThread = 8ull << 20;
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t parts = std::min<size_t>(std::min<size_t>(8, hw), n / kPerThread);
+  if (parts < 2) {
+    unpack_range(dst, bits, 0, n);
+    return;
+  }
+  const size_t step = (n / parts + 4095) & ~size_t(4095);
+  std::vector<std::thread> th;
+  try {
+    for (size_t i = 1; i < parts && i * step < n; ++i)
+      th.emplace_back([=] { unpack_range(dst, bits, i * step, std::min(n, (i + 1) * step)); });
+  } catch (...) {
+    // no thread available: the remaining parts are unpacked below
+  }
+  unpack_range(dst, bits, 0, std::min(n, step));
+  for (size_t i = th.size() + 1; i < parts && i * step < n; ++i)
+    unpack_range(dst, bits, i * step, std::min(n, (i + 1) * step));
+  for (auto &t : th) t.join();
+}
+
 // Wait for a stage's last chunk and move its answers to the caller's buffer.
 int finish_slot(PipeSlot &ps) {
   if (!ps.pending) return SBF_OK;
   ps.pending = false;
   SBF_HIP(hipEventSynchronize(ps.done), "kernel execution");
-  if (ps.flush_dst && ps.flush_len) host_copy(ps.flush_dst, ps.h_out.ptr, ps.flush_len);
+  if (ps.flush_dst && ps.flush_len) {
+    if (ps.flush_packed)
+      unpack_bits(ps.flush_dst, (const uint8_t *)ps.h_out.ptr, ps.flush_len);
+    else
+      host_copy(ps.flush_dst, ps.h_out.ptr, ps.flush_len);
+  }
   ps.flush_dst = nullptr;
   ps.flush_len = 0;
+  ps.flush_packed = false;
   return SBF_OK;
 }
 
@@ -357,6 +413,7 @@ int drain_pipe(sbf_filter *f, int rc) {
     if (ps.stream) (void)hipStreamSynchronize(ps.stream);
     ps.pending = false;
     ps.flush_dst = nullptr;
+    ps.flush_packed = false;
   }
   (void)hipGetLastError();
   return rc;
@@ -366,10 +423,12 @@ int drain_pipe(sbf_filter *f, int rc) {
 // `staging` bases whose k-mer starts partition [0, total); a chunk carries
 // k-1 extra bases.  Chunk c runs on pipeline stage c mod 2: the caller's bases
 // are copied into pinned memory (or sent directly when the caller's buffer is
-// pinned), sent to the device, marked, and inserted or queried; answers come
-// back the same way.  The kernels of successive chunks are ordered by events,
-// so inserts never overlap one another.  Queries write answers for k-mer
-// starts [0, n_out).
+// pinned), sent to the device, marked, and inserted or queried.  With the
+// lane query, answers come back as bits (an eighth of the bytes over the host
+// link) and are spread to bytes on the host; otherwise as bytes, copied like
+// the input.  The kernels of successive chunks are ordered by events, so
+// inserts never overlap one another.  Queries write answers for k-mer starts
+// [0, n_out).
 int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nrec, uint8_t *out, uint64_t n_out,
                bool query) {
   // earlier stream-ordered work on any stream may still use the filter
@@ -379,9 +438,12 @@ int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nre
   const uint64_t k = f->g.k;
   const uint64_t total = off[nrec];
   const uint64_t budget = std::max<uint64_t>(f->staging, 4096);
-  const uint64_t span = budget - (k - 1);  // k-mer starts per chunk
+  const bool packed = query && use_rolling(f) && sbf::query_packed_supported(query_kernel_mode(f));
+  // k-mer starts per chunk; a multiple of 64 when answers travel as bits, so
+  // that every chunk's bits start on a byte
+  const uint64_t span = packed ? (budget - (k - 1)) & ~63ull : budget - (k - 1);
   const bool in_direct = host_pinned(seq);
-  const bool out_direct = query && host_pinned(out);
+  const bool out_direct = query && !packed && host_pinned(out);
   hipEvent_t prev_kernel = nullptr;
   uint64_t r0 = 0;  // first record overlapping the chunk
   int si = 0;
@@ -428,6 +490,7 @@ int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nre
       if ((rc = grow(ps.d_out, budget + 64, "staging buffer"))) return drain_pipe(f, rc);
       a.out = (uint8_t *)ps.d_out.ptr;
       a.n_out = c1 - c0;
+      a.packed = packed ? 1 : 0;
       rc = run_query(f, a, st);
     } else {
       rc = run_insert(f, a, st);
@@ -437,13 +500,17 @@ int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nre
     prev_kernel = ps.kernel_done;
     if (query && o1 > c0) {
       uint8_t *dst = out + c0;
+      uint64_t nbytes = o1 - c0;
       if (!out_direct) {
-        if ((rc = grow_pinned(ps.h_out, budget + 64, "pinned staging buffer"))) return drain_pipe(f, rc);
+        if ((rc = grow_pinned(ps.h_out, (packed ? budget / 8 : budget) + 64, "pinned staging buffer")))
+          return drain_pipe(f, rc);
         ps.flush_dst = dst;
         ps.flush_len = o1 - c0;
+        ps.flush_packed = packed;
         dst = (uint8_t *)ps.h_out.ptr;
+        if (packed) nbytes = (o1 - c0 + 7) / 8;
       }
-      e = hipMemcpyAsync(dst, ps.d_out.ptr, o1 - c0, hipMemcpyDeviceToHost, st);
+      e = hipMemcpyAsync(dst, ps.d_out.ptr, nbytes, hipMemcpyDeviceToHost, st);
       if (e != hipSuccess) return drain_pipe(f, hip_error(e, "copy answers to host"));
     }
     if ((e = hipEventRecord(ps.done, st)) != hipSuccess) return drain_pipe(f, hip_error(e, "event record"));

@@ -23,6 +23,9 @@ struct SeqArgs {
   const uint32_t *starts;  // record-start bits (1 bit per base) or null
   uint8_t *out;            // query only
   uint64_t n_out;          // query only
+  // query only: out holds one bit per k-mer start (bit i%8 of byte i/8), ceil(n_out/8) bytes;
+  // supported by the lane-sequential rolling query only (query_packed_supported)
+  int packed = 0;
 };
 
 // Insert strategies of the rolling kernels: two passes (plain read-modify-write,
@@ -40,6 +43,8 @@ constexpr int kQueryDirectMode = 2;
 
 // Rolling kernels exist for a few compiled parameter sets.
 bool rolling_supported(const Geometry &g);
+// Query organisations that can write answers as bits (SeqArgs::packed).
+inline bool query_packed_supported(int mode) { return mode == kQueryLaneMode; }
 
 // Launch shape of the rolling kernels: one workgroup per tile, or a
 // persistent grid of persistent_wgs workgroups that take tiles from device
