@@ -72,6 +72,44 @@ def kmer_positions(off: np.ndarray, k: int) -> int:
     return int(np.maximum(lens - k + 1, 0).sum())
 
 
+_ACGT = np.zeros(256, dtype=np.bool_)
+_ACGT[np.frombuffer(b"ACGTacgt", dtype=np.uint8)] = True
+
+
+def valid_kmers(seq: np.ndarray, off: np.ndarray, k: int, chunk: int = 1 << 28) -> int:
+    """k-mer positions whose k bases are all A/C/G/T (either case), counted
+    per record; equal to kmer_positions when the sequence has no other byte."""
+    bad = sum(int(np.count_nonzero(~_ACGT[seq[i:i + chunk]])) for i in range(0, seq.size, chunk))
+    if bad == 0:
+        return kmer_positions(off, k)
+    total = 0
+    for r in range(off.size - 1):
+        a, b = int(off[r]), int(off[r + 1])
+        if b - a < k:
+            continue
+        inv = np.concatenate(([0], np.cumsum(~_ACGT[seq[a:b]], dtype=np.int64)))
+        total += int(np.count_nonzero(inv[k:] == inv[:-k]))
+    return total
+
+
+def host_cpu() -> dict:
+    """CPU model and the number of CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 0
+    return {"cpu_model": model, "host_cpus": n}
+
+
 def workload(name: str):
     if name == "in_cache":
         return synth.in_cache_workload()
@@ -128,7 +166,7 @@ def cpu_baseline(w, budget_s: float = 12.0):
         t_q += time.perf_counter() - t0
         k_q += kmer_positions(o_, k)
     total = t_ins + t_q
-    return {"value": (k_ins + k_q) / total, "unit": "k-mers/s", "cores": 1, "kind": "oracle",
+    return {"value": (k_ins + k_q) / total, "unit": "k-mers/s", "cores": 1, "kind": "oracle", **host_cpu(),
             "sample": "%d k-mers inserted (first %d bases of contig 0) + %d k-mers queried (%d+%d reads); "
                       "insert %.3g k-mers/s, query %.3g k-mers/s" % (
                           k_ins, n_ins, k_q, take[0][1] - take[0][0], take[1][1] - take[1][0],
@@ -822,6 +860,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "k": w["k"], "s": w["s"], "m": w["m"], "H": w["H"],
                    "filter_bits": f.num_bits, "insert_kmers": n_ins_kmers, "query_kmers": n_q_kmers,
+                   "insert_valid_kmers": valid_kmers(ins, ioff, k), "query_valid_kmers": valid_kmers(qs, qoff, k),
                    "parallelism": "single GPU"},
         "p50_batch_ms": round(float(np.percentile(step_ms, 50)), 4),
         "p99_batch_ms": round(float(np.percentile(step_ms, 99)), 4),

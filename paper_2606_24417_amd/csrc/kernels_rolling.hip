@@ -187,6 +187,12 @@ __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uin
         old[k][3] = ((uint64_t)hi.w << 32) | hi.z;
       }
     }
+    // Wait for the loads here, on every path: the stores below are
+    // conditional, and a load the compiler still counts as outstanding after
+    // them would make the next write of its register wait for the stores too
+    // (the vector-memory counter retires in order).  s_waitcnt vmcnt(0), the
+    // other counters left at their maxima.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     // a later buffered segment on the same shard carries the earlier masks,
     // since its read does not see the earlier write of this lane
 #pragma unroll
