@@ -101,8 +101,9 @@ int sbf_query_seq(sbf_filter *f, const char *seq, uint64_t len, uint8_t *out);
  * until the next call into the library on this thread. */
 int sbf_last_error(const char **msg);
 
-/* Geometry: number of shards N, filter size in bits (256 * N) and number of
- * 64-bit words (4 * N).  0 for a NULL filter. */
+/* Geometry: number of shards N, filter size in bits (64 * S * N for shards
+ * of S words: 256 * N for sbf_create) and number of 64-bit words (S * N).
+ * 0 for a NULL filter. */
 uint64_t sbf_num_shards(const sbf_filter *f);
 uint64_t sbf_num_bits(const sbf_filter *f);
 uint64_t sbf_num_words(const sbf_filter *f);
@@ -118,7 +119,7 @@ int sbf_set_bits(sbf_filter *f, const uint64_t *host_src, uint64_t nwords);
  * not synchronise. */
 int sbf_clear(sbf_filter *f, void *stream);
 
-/* Device pointer of the bit array (4 * N words).  Valid until sbf_destroy. */
+/* Device pointer of the bit array (S * N words).  Valid until sbf_destroy. */
 const uint64_t *sbf_device_words(const sbf_filter *f);
 
 /* Stream-ordered forms of sbf_insert_seq / sbf_query_seq on device memory
@@ -183,7 +184,7 @@ int sbf_get_variant(const sbf_filter *f); /* the family in effect (1 or 2) */
 int sbf_set_insert_mode(sbf_filter *f, int mode);
 
 /* How the rolling query kernel is organised:
- *   SBF_QUERY_LANE (default): each lane walks 32 consecutive k-mers, builds
+ *   SBF_QUERY_LANE (default): each lane walks 48 consecutive k-mers, builds
  *     the mask of each k-mer's (k-s+1)*H bits from its s-mers and tests it
  *     one k-mer later against the k-mer's shard, which the lane loads only
  *     where the shard changes (once per super-k-mer);
