@@ -120,9 +120,31 @@ def workload(name: str):
     raise SystemExit("unknown workload %s" % name)
 
 
+def _insert_pieces(ioff: np.ndarray, total: int, n_pieces: int, k: int):
+    """Split bases [0, total) of a record batch into n_pieces ranges whose
+    k-mer starts partition [0, total - k + 1); each range carries k-1 extra
+    bases and the record starts that fall inside it (local offsets)."""
+    cuts = np.linspace(0, max(total - k + 1, 0), n_pieces + 1).astype(np.int64)
+    out = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        if b <= a:
+            continue
+        end = min(total, int(b) + k - 1)
+        inner = ioff[(ioff > a) & (ioff < end)].astype(np.int64) - int(a)
+        loc = np.concatenate(([0], inner, [end - int(a)])).astype(np.uint64)
+        out.append((int(a), end, loc))
+    return out
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
-    """The oracle (plain C, one thread) on a bounded sample of the workload:
-    the first contig prefix inserted and the first reads queried."""
+    """The oracle (plain C, unchanged) on a bounded sample of the workload,
+    timed on one thread and on every CPU this process may use.  The parallel
+    run calls the same C functions from Python threads (ctypes releases the
+    GIL): the insert splits the sample into pieces, each inserted into a
+    filter of its own, and ORs the filters (the OR is timed); the query splits
+    the reads over the threads against the one filter."""
+    import threading
+
     import oracle
 
     k = w["k"]
@@ -130,46 +152,90 @@ def cpu_baseline(w, budget_s: float = 12.0):
     ins, ioff = w["insert"]
     qs, qoff = w["query"]
     F = p.empty()
-    # calibrate on a small prefix, then size the sample to the time budget
+    # calibrate on a small prefix, then size the samples to the time budget
     n_cal = min(200_000, ins.size)
     t0 = time.perf_counter()
     oracle.insert(p, F, ins[:n_cal])
     t_cal = max(1e-6, time.perf_counter() - t0)
     per_kmer = t_cal / max(1, n_cal - k + 1)
-    n_ins = int(min(ins.size, max(n_cal, 0.5 * budget_s / per_kmer)))
+    # one thread: a prefix of contig 0 inserted, whole reads queried
+    n_ins = int(min(ins.size, max(n_cal, 0.25 * budget_s / per_kmer)))
     n_ins = min(n_ins, int(ioff[1]) if ioff.size > 1 else ins.size)
     F[:] = 0
     t0 = time.perf_counter()
     oracle.insert(p, F, ins[:n_ins])
     t_ins = time.perf_counter() - t0
     k_ins = max(0, n_ins - k + 1)
-    # queries: whole reads from the front of the batch, positives and negatives
     nrec = qoff.size - 1
-    half = int(0.5 * budget_s / per_kmer)
-    take = []
-    acc = 0
-    for start in (0, nrec // 2):
-        r = start
-        got = 0
-        while r < nrec and got < half // 2:
-            got += max(0, int(qoff[r + 1] - qoff[r]) - k + 1)
-            r += 1
-        take.append((start, r))
-        acc += got
-    q_parts = [qs[int(qoff[a]):int(qoff[b])] for a, b in take]
-    o_parts = [qoff[a:b + 1] - qoff[a] for a, b in take]
+
+    def reads(kmers, starts=(0, nrec // 2)):
+        # whole reads from each start, up to the next start
+        take = []
+        bounds = list(starts) + [nrec]
+        for start, stop in zip(bounds[:-1], bounds[1:]):
+            r, got = start, 0
+            while r < stop and got < kmers // len(starts):
+                got += max(0, int(qoff[r + 1] - qoff[r]) - k + 1)
+                r += 1
+            take.append((start, r))
+        return take
+
+    take = reads(int(0.25 * budget_s / per_kmer))
     t_q = 0.0
     k_q = 0
-    for s_, o_ in zip(q_parts, o_parts):
+    for a, b in take:
+        s_, o_ = qs[int(qoff[a]):int(qoff[b])], qoff[a:b + 1] - qoff[a]
         t0 = time.perf_counter()
         oracle.query(p, F, s_, o_)
         t_q += time.perf_counter() - t0
         k_q += kmer_positions(o_, k)
-    total = t_ins + t_q
-    return {"value": (k_ins + k_q) / total, "unit": "k-mers/s", "cores": 1, "kind": "oracle", **host_cpu(),
-            "sample": "%d k-mers inserted (first %d bases of contig 0) + %d k-mers queried (%d+%d reads); "
-                      "insert %.3g k-mers/s, query %.3g k-mers/s" % (
-                          k_ins, n_ins, k_q, take[0][1] - take[0][0], take[1][1] - take[1][0],
+    single = (k_ins + k_q) / (t_ins + t_q)
+
+    # every CPU: a larger sample, split over the threads
+    nt = host_cpu()["host_cpus"] or 1
+    n_ins_mt = int(min(ins.size, max(n_ins, nt * 0.25 * budget_s / per_kmer)))
+    pieces = _insert_pieces(ioff, n_ins_mt, nt, k)
+    filters = [p.empty() for _ in pieces]
+    for G in filters:
+        G[:] = 0  # touch the pages outside the timed region
+
+    def run_threads(fns):
+        th = [threading.Thread(target=fn) for fn in fns]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+
+    def or_slice(lo, hi):
+        for G in filters[1:]:
+            np.bitwise_or(filters[0][lo:hi], G[lo:hi], out=filters[0][lo:hi])
+
+    cut = np.linspace(0, p.nwords, nt + 1).astype(np.int64)
+    t0 = time.perf_counter()
+    run_threads([lambda a=a, e=e, loc=loc, G=G: oracle.insert(p, G, ins[a:e], loc)
+                 for (a, e, loc), G in zip(pieces, filters)])
+    run_threads([lambda lo=int(lo), hi=int(hi): or_slice(lo, hi) for lo, hi in zip(cut[:-1], cut[1:])])
+    t_ins_mt = time.perf_counter() - t0
+    Fm = filters[0]
+    k_ins_mt = kmer_positions(ioff[ioff <= n_ins_mt] if ioff[-1] <= n_ins_mt else
+                              np.concatenate((ioff[ioff < n_ins_mt], [n_ins_mt])), k)
+    del filters
+    q_kmers = min(int(nt * 0.25 * budget_s / per_kmer), kmer_positions(qoff, k))
+    take_mt = reads(q_kmers, starts=tuple(int(x) for x in np.linspace(0, nrec, 2 * nt, endpoint=False)))
+    parts = [(qs[int(qoff[a]):int(qoff[b])], qoff[a:b + 1] - qoff[a]) for a, b in take_mt if b > a]
+    t0 = time.perf_counter()
+    run_threads([lambda s_=s_, o_=o_: oracle.query(p, Fm, s_, o_) for s_, o_ in parts])
+    t_q_mt = time.perf_counter() - t0
+    k_q_mt = sum(kmer_positions(o_, k) for _, o_ in parts)
+    multi = (k_ins_mt + k_q_mt) / (t_ins_mt + t_q_mt)
+    return {"value": multi, "unit": "k-mers/s", "cores": nt, "kind": "oracle", **host_cpu(),
+            "single_thread_value": single,
+            "sample": "%d threads: %d k-mers inserted (first %d bases of the genome, %d pieces, filters OR-ed) + "
+                      "%d k-mers queried (%d reads), insert %.3g k-mers/s, query %.3g k-mers/s; one thread: %d "
+                      "k-mers inserted (first %d bases of contig 0) + %d queried, insert %.3g k-mers/s, "
+                      "query %.3g k-mers/s" % (
+                          nt, k_ins_mt, n_ins_mt, len(pieces), k_q_mt, sum(b - a for a, b in take_mt),
+                          k_ins_mt / t_ins_mt, k_q_mt / max(t_q_mt, 1e-9), k_ins, n_ins, k_q,
                           k_ins / t_ins, k_q / max(t_q, 1e-9))}
 
 

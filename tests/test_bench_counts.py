@@ -25,3 +25,23 @@ def test_valid_kmers_all_valid_equals_positions():
     seq = np.frombuffer(b"ACGT" * 250, dtype=np.uint8)
     off = np.array([0, 10, 500, 1000], dtype=np.uint64)
     assert bench.valid_kmers(seq, off, 31) == bench.kmer_positions(off, 31) == (500 - 10 - 30) + (500 - 30)
+
+
+def test_parallel_baseline_pieces_equal_one_insert():
+    """The CPU baseline's parallel insert (pieces with k-1 overlap and their
+    record starts, filters OR-ed) builds the filter of one serial insert."""
+    import oracle
+
+    rng = np.random.default_rng(3)
+    ins = rng.choice(np.frombuffer(b"ACGTN", dtype=np.uint8), size=120_000,
+                     p=[.24, .24, .24, .24, .04]).astype(np.uint8)
+    ioff = np.array([0, 1000, 1010, 50_000, 50_030, 90_000, 120_000], dtype=np.uint64)
+    p = oracle.Params(31, 28, 16, 4, 1 << 20)
+    for total in (120_000, 61_237):
+        clip = ioff[ioff <= total] if ioff[-1] <= total else np.concatenate((ioff[ioff < total], [total]))
+        want = oracle.insert(p, p.empty(), ins[:total], clip.astype(np.uint64))
+        for n in (1, 3, 16):
+            got = p.empty()
+            for a, e, loc in bench._insert_pieces(ioff, total, n, 31):
+                got |= oracle.insert(p, p.empty(), ins[a:e], loc)
+            assert np.array_equal(got, want), (total, n)
