@@ -759,15 +759,17 @@ constexpr int kQueryLaneWG = 256;
 constexpr int kQueryLaneD = 1;
 
 // Grid of a launch over ntiles tiles: one workgroup per tile, or a persistent
-// grid that takes tiles from the queue counter `slot` (reset first).
+// grid that takes tiles from the queue counter `slot` (reset first).  A batch
+// of no more tiles than the persistent grid has workgroups runs as a plain
+// launch: the same tiles, one per workgroup, without the counter reset.
 hipError_t tile_grid(uint64_t ntiles, const LaunchShape &ls, int slot, hipStream_t st, TileQueue &tq,
                      unsigned &grid) {
   tq.counter = nullptr;
   tq.ntiles = (uint32_t)ntiles;
   grid = (unsigned)ntiles;
-  if (ls.queue != nullptr && ls.persistent_wgs != 0) {
+  if (ls.queue != nullptr && ls.persistent_wgs != 0 && ntiles > ls.persistent_wgs) {
     tq.counter = ls.queue + slot;
-    grid = (unsigned)(ntiles < ls.persistent_wgs ? ntiles : ls.persistent_wgs);
+    grid = ls.persistent_wgs;
     return launch_fill_u32(tq.counter, 1, 0u, st);
   }
   return hipSuccess;

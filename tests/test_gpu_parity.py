@@ -513,8 +513,11 @@ def test_query_modes_match_oracle(qmode):
 @pytest.mark.parametrize("wgs", [0, 1, 4])
 def test_persistent_launch_shapes_match_oracle(wgs):
     """Persistent grids taking tiles from the device work queue give the
-    same filter and answers as one workgroup per tile."""
-    w = synth.in_cache_workload(scale=0.01)
+    same filter and answers as one workgroup per tile.  The batches have
+    more tiles than the persistent grids have workgroups (1220 insert and
+    2441 query tiles against 256 and 1024), so workgroups take several
+    tiles from the queue."""
+    w = synth.in_cache_workload(scale=0.1)
     params = (w["k"], w["s"], w["m"], w["H"], w["bits"])
     ob, oa = oracle_run(params, [w["insert"]], w["query"])
     for qmode in (0, 1, 2):
