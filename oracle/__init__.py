@@ -29,13 +29,32 @@ _u32 = ctypes.c_uint32
 _u64 = ctypes.c_uint64
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle into ``oracle/liboracle.so`` with gcc."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC])
-        os.replace(tmp, _LIB)
-    return _LIB
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+# gcc flags of the checked build: AddressSanitizer and UndefinedBehaviorSanitizer,
+# any finding fatal (the process aborts, so the calling test fails)
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
+
+
+def sanitized() -> bool:
+    """True when this process is to load the sanitizer build (environment
+    variable SBF_ORACLE_SANITIZE=1; the sanitizer runtimes must then be
+    preloaded, since the Python interpreter is not built with them)."""
+    return os.environ.get("SBF_ORACLE_SANITIZE") == "1"
+
+
+def build(force: bool = True, sanitize: bool | None = None) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` with gcc, or with
+    ``sanitize`` into ``oracle/liboracle_san.so`` under ASan and UBSan."""
+    if sanitize is None:
+        sanitize = sanitized()
+    out = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        flags = SANITIZE_FLAGS if sanitize else ["-O2"]
+        subprocess.check_call(["gcc"] + flags + ["-std=c99", "-Wall", "-Werror", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -44,8 +63,7 @@ _lib = None
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        build(force=False)
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(build(force=False))
         L.orc_base_code.argtypes = [ctypes.c_ubyte]
         L.orc_base_code.restype = ctypes.c_int
         L.orc_hash_minimizer.argtypes = [_u64]
@@ -66,8 +84,6 @@ def lib() -> ctypes.CDLL:
         L.orc_insert_records.restype = None
         L.orc_query_records.argtypes = [_u32, _u32, _u32, _u32, _u32, _u64, _u64p, _u8p, _u64p, _u64, _u8p]
         L.orc_query_records.restype = None
-        L.orc_query_positions.argtypes = [_u32, _u32, _u32, _u32, _u32, _u64, _u64p, _u8p, _u64, _u64p, _u64, _u8p]
-        L.orc_query_positions.restype = None
         L.orc_kmer_shards.argtypes = [_u32, _u32, _u64, _u8p, _u64, _u64p]
         L.orc_kmer_shards.restype = None
         L.orc_kmer_min_hashes.argtypes = [_u32, _u32, _u8p, _u64, _u64p, _u8p]
@@ -173,16 +189,6 @@ def query(p: Params, F: np.ndarray, seq, offsets=None, per_base: bool | None = N
                             _p(s, _u8p), _p(off, _u64p), off.size - 1, _p(out, _u8p))
     if single if per_base is None else not per_base:
         return out[: max(0, s.size - p.k + 1)]
-    return out
-
-
-def query_positions(p: Params, F: np.ndarray, seq, positions) -> np.ndarray:
-    s = _u8(seq)
-    pos = np.ascontiguousarray(positions, dtype=np.uint64)
-    out = np.zeros(pos.size, dtype=np.uint8)
-    F = np.ascontiguousarray(F)
-    lib().orc_query_positions(p.k, p.s, p.m, p.H, p.shard_words, p.nshards, _p(F, _u64p),
-                              _p(s, _u8p), s.size, _p(pos, _u64p), pos.size, _p(out, _u8p))
     return out
 
 

@@ -223,21 +223,6 @@ void orc_query_records(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint32_t 
     }
 }
 
-/* Query the k-mers starting at the given positions of one record seq[0..len)
- * only (for sampled checks on large inputs). */
-void orc_query_positions(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint32_t S,
-                         uint64_t nshards, const uint64_t *F, const unsigned char *seq,
-                         uint64_t len, const uint64_t *pos, uint64_t npos, uint8_t *out)
-{
-    orc_params p = {k, s, m, H, S, nshards};
-    for (uint64_t n = 0; n < npos; n++) {
-        uint64_t i = pos[n], K;
-        out[n] = 0;
-        if (i + k <= len && orc_pack(seq + i, k, &K))
-            out[n] = (uint8_t)orc_contains_kmer(&p, F, K);
-    }
-}
-
 /* Shard index of the k-mer at every position (UINT64_MAX when invalid). */
 void orc_kmer_shards(uint32_t k, uint32_t m, uint64_t nshards, const unsigned char *seq,
                      uint64_t len, uint64_t *shard)

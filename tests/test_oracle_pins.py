@@ -98,6 +98,44 @@ def test_bit_address_is_low_six_bits_of_slice(H):
             assert oracle.word_index(g, t, H, 4) == t % 4
 
 
+# Known answers of the salted bit address for narrow slices (64 // H < 6,
+# i.e. H >= 11): beta_t(g) = top 6 bits of g * salt_t mod 2^64 with
+# salt_t = floor(2^64/phi) * (2t + 1) mod 2^64 (Section "Optimizations":
+# a golden-ratio-derived salt when the slices are too narrow for a 6-bit
+# address).  The rows were written out with Python integers, t = 0 .. 15.
+SALTED_BETA = {
+    0x0123456789ABCDEF: [3, 9, 15, 22, 28, 34, 40, 47, 53, 59, 2, 8, 14, 20, 27, 33],
+    0xFFFFFFFFFFFFFFFF: [24, 9, 58, 43, 28, 12, 61, 46, 31, 16, 1, 50, 35, 20, 4, 53],
+    0x8000000000000001: [7, 22, 37, 52, 3, 19, 34, 49, 0, 15, 30, 45, 60, 11, 27, 42],
+    0xDEADBEEFCAFEF00D: [23, 6, 53, 36, 20, 3, 50, 33, 16, 63, 46, 29, 13, 60, 43, 26],
+}
+
+
+@pytest.mark.parametrize("H", [11, 12, 13, 16])
+def test_salted_bit_address_known_answers(H):
+    """H >= 11 leaves slices narrower than 6 bits, so each hash index takes the
+    top 6 bits of the hash times its own odd golden-ratio salt.  Checked
+    against the written-out table, and by hand on two inputs: g = 1 gives the
+    top bits of the salt itself, and g = 2^63 + 1 adds 2^63 to it (an odd salt
+    times 2^63 is 2^63 mod 2^64), flipping only the top bit of the address.
+    The salt for t is (2t + 1) times the minimizer multiplier, so beta_t(g) is
+    also the top 6 bits of the (pinned) minimizer hash of (2t + 1) g."""
+    for g, row in SALTED_BETA.items():
+        for t in range(H):
+            assert oracle.bit_address(g, t, H) == row[t], (hex(g), t)
+            assert oracle.word_index(g, t, H, 4) == t % 4
+    for t in range(H):
+        top = oracle.bit_address(1, t, H)
+        assert oracle.bit_address((1 << 63) + 1, t, H) == top ^ 32
+        assert top == oracle.hash_minimizer(2 * t + 1) >> 58
+    assert oracle.bit_address(1, 0, H) == 0x9E3779B97F4A7C15 >> 58 == 39
+    rng = np.random.default_rng(H)
+    for _ in range(200):
+        g = int(rng.integers(0, 1 << 63)) * 2 + int(rng.integers(0, 2))
+        for t in range(H):
+            assert oracle.bit_address(g, t, H) == oracle.hash_minimizer(((2 * t + 1) * g) & MASK64) >> 58
+
+
 def test_word_index_groups_for_wider_shards():
     rng = np.random.default_rng(7)
     for S, gbits in ((8, 1), (16, 2)):
@@ -324,6 +362,82 @@ def test_short_and_empty_inputs():
     assert oracle.query(p, F, "").size == 0
     out = oracle.query(p, F, "A" * 40 + "C" * 10, [0, 0, 20, 50, 50])
     assert out.size == 50 and not out.any()
+
+
+def test_record_ends_answer_zero_on_a_nonempty_filter():
+    """Answers are per base position; the last k-1 positions of each record
+    (and every position of a record shorter than k) answer 0 even when the
+    k-mer that starts there and runs into the next record is in the filter
+    (Section "Sequence-Native Design": no k-mer spans two records; Algorithm 2
+    writes false for an invalid k-mer).  The concatenation of the records is
+    inserted as one record, so every spanning k-mer is present; with 2^30 bits
+    the answers are exact membership, computed here from string slices."""
+    rng = np.random.default_rng(24)
+    k = 31
+    p = oracle.Params(k, 28, 16, 4, 1 << 30)
+    lengths = [45, 0, 31, 5, 32, 100, 30, 64, 1, 40]
+    recs = [rand_dna(rng, n, "ACGT" * 20 + "N") for n in lengths]
+    seq = "".join(recs)
+    off = np.concatenate(([0], np.cumsum(lengths))).astype(np.uint64)
+    F = oracle.insert(p, p.empty(), seq)          # one record: spanning k-mers inserted
+    present = {seq[i:i + k] for i in range(len(seq) - k + 1) if "N" not in seq[i:i + k]}
+    out = oracle.query(p, F, seq, off)
+    assert out.size == len(seq)
+    want = []
+    for r in recs:
+        for i in range(len(r)):
+            kmer = r[i:i + k]
+            want.append(int(len(kmer) == k and kmer in present))
+    assert out.tolist() == want
+    # the spanning k-mers themselves answer 1 when queried as one record
+    whole = oracle.query(p, F, seq)
+    assert whole.tolist() == [int(seq[i:i + k] in present) for i in range(len(seq) - k + 1)]
+    assert int(whole.sum(dtype=np.int64)) > sum(want)
+
+
+def brute_segments(recs, k, m, nshards):
+    """Maximal runs of consecutive valid k-mers of one record with one shard,
+    from string slices (a k-mer with a byte outside ACGTacgt is invalid and
+    ends the run; a record start ends it too)."""
+    lengths = []
+    for rec in recs:
+        prev = None
+        for i in range(len(rec) - k + 1):
+            kmer = rec[i:i + k]
+            if any(c not in "ACGTacgt" for c in kmer):
+                prev = None
+                continue
+            sh = brute_min_hash(kmer.upper(), m) & (nshards - 1)
+            if prev is not None and sh == prev:
+                lengths[-1] += 1
+            else:
+                lengths.append(1)
+            prev = sh
+    return lengths
+
+
+@pytest.mark.parametrize("bits", [256, 1024, 1 << 14, 1 << 40])
+def test_segment_count_brute_force_with_invalid_bases_and_records(bits):
+    """Super-k-mer segments (one shard access each; the denominators of the
+    out-of-cache rooflines) against a brute-force count over string slices, on
+    record batches with N bases and short records.  With one or four shards
+    nearly every pair of neighbouring k-mers shares a shard, so a run that
+    failed to end at an invalid k-mer or at a record start would change the
+    count."""
+    rng = np.random.default_rng(bits % 1000 + 25)
+    k, m = 31, 16
+    p = oracle.Params(k, 28, m, 4, bits)
+    for trial in range(6):
+        lengths = [int(x) for x in rng.integers(0, 140, 12)] + [31, 32, 30]
+        recs = [rand_dna(rng, n, "ACGT" * 12 + "Nn") for n in lengths]
+        rng.shuffle(recs)
+        seq = "".join(recs)
+        off = np.concatenate(([0], np.cumsum([len(r) for r in recs]))).astype(np.uint64)
+        want = brute_segments(recs, k, m, p.nshards)
+        n, got = oracle.count_segments(p, seq, off, with_lengths=True)
+        assert n == len(want)
+        assert got.tolist() == want
+        assert oracle.count_segments(p, seq, off) == len(want)
 
 
 # --- worked examples of the paper --------------------------------------------
