@@ -5,7 +5,12 @@ contigs), query a batch of reads; all on device-resident input, on torch's
 current stream.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
-                  [--workload in_cache|out_of_cache|tiny] [--no-cpu-baseline]
+                  [--workload out_of_cache|in_cache|tiny|batched|served|host|sweep]
+                  [--no-cpu-baseline] [--no-in-cache]
+
+The default workload is the out-of-cache one (3 Gbp genome into an 8 GiB
+filter, 10M short + 100k long reads); its line carries the in-cache workload
+(100 Mbp into 256 MiB) as a second key.
 """
 
 from __future__ import annotations
@@ -120,123 +125,119 @@ def workload(name: str):
     raise SystemExit("unknown workload %s" % name)
 
 
-def _insert_pieces(ioff: np.ndarray, total: int, n_pieces: int, k: int):
-    """Split bases [0, total) of a record batch into n_pieces ranges whose
-    k-mer starts partition [0, total - k + 1); each range carries k-1 extra
-    bases and the record starts that fall inside it (local offsets)."""
-    cuts = np.linspace(0, max(total - k + 1, 0), n_pieces + 1).astype(np.int64)
-    out = []
-    for a, b in zip(cuts[:-1], cuts[1:]):
-        if b <= a:
-            continue
-        end = min(total, int(b) + k - 1)
-        inner = ioff[(ioff > a) & (ioff < end)].astype(np.int64) - int(a)
-        loc = np.concatenate(([0], inner, [end - int(a)])).astype(np.uint64)
-        out.append((int(a), end, loc))
-    return out
+def _prefix_batch(seq, off, n):
+    """The first n bases of a record batch, with its offsets clipped."""
+    n = int(min(n, seq.size))
+    o = off.astype(np.uint64)
+    return seq[:n], np.concatenate((o[o < n], [np.uint64(n)]))
+
+
+def cpu_query_sample(w, ins_prefix, kmers, seed):
+    """A bounded sample of the workload's query batch with about `kmers` k-mer
+    positions: from every read class (short and long reads), the same share
+    of reads as in the workload; negatives are the workload's own negative
+    reads, positives are fresh reads of the same lengths drawn (with the same
+    1% substitutions) from the inserted genome prefix, so that they are
+    present in the sample's filter as the workload's positives are in the full
+    filter."""
+    qs, qoff = w["query"]
+    k = w["k"]
+    lens = np.diff(qoff.astype(np.int64))
+    total = kmer_positions(qoff, k)
+    frac = min(1.0, kmers / max(1, total))
+    pseq, poff = ins_prefix
+    longest = int(np.diff(poff.astype(np.int64)).max())
+
+    def take(first, end):
+        # reads of the class, or a cut of its first read when the class has
+        # too few reads for the sample's share
+        want = (end - first) * frac
+        if want >= 1:
+            n = int(round(want))
+            return lens[first:first + n]
+        return np.array([max(k, int(lens[first] * want))], dtype=np.int64)
+
+    parts = []
+    for ci, (p0, p1, n0, n1) in enumerate(w["read_classes"]):
+        plen = np.minimum(take(p0, p1), longest)
+        parts.append(synth.sample_reads(pseq, poff, plen.size, plen, seed + ci))
+        nlen = take(n0, n1)
+        a = int(qoff[n0])
+        noff = np.concatenate(([0], np.cumsum(nlen))).astype(np.uint64)
+        parts.append((qs[a:a + int(noff[-1])], noff))
+    return synth.concat(*parts)
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
-    """The oracle (plain C, unchanged) on a bounded sample of the workload,
-    timed on one thread and on every CPU this process may use.  The parallel
-    run calls the same C functions from Python threads (ctypes releases the
-    GIL): the insert splits the sample into pieces, each inserted into a
-    filter of its own, and ORs the filters (the OR is timed); the query splits
-    the reads over the threads against the one filter."""
-    import threading
-
+    """The oracle (plain C, unchanged arithmetic) on a bounded sample of the
+    workload, timed on one thread and on every CPU this process may use, with
+    one filter of the workload's full size (out of cache for the large
+    workloads) that all threads share: the insert runs the oracle's
+    shared-filter entry point (the same per-k-mer definition with atomic ORs)
+    over k-1-overlapping pieces, the query splits the sample's reads over the
+    threads.  About budget_s seconds of wall time in the timed regions."""
     import oracle
 
     k = w["k"]
     p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
     ins, ioff = w["insert"]
-    qs, qoff = w["query"]
-    F = p.empty()
+    nt = host_cpu()["host_cpus"] or 1
+    F = np.zeros(p.nwords, dtype=np.uint64)
+    F[:] = 0  # touch the pages outside the timed regions
     # calibrate on a small prefix, then size the samples to the time budget
     n_cal = min(200_000, ins.size)
     t0 = time.perf_counter()
     oracle.insert(p, F, ins[:n_cal])
-    t_cal = max(1e-6, time.perf_counter() - t0)
-    per_kmer = t_cal / max(1, n_cal - k + 1)
-    # one thread: a prefix of contig 0 inserted, whole reads queried
-    n_ins = int(min(ins.size, max(n_cal, 0.25 * budget_s / per_kmer)))
-    n_ins = min(n_ins, int(ioff[1]) if ioff.size > 1 else ins.size)
+    per_kmer = max(1e-6, time.perf_counter() - t0) / max(1, n_cal - k + 1)
+    share = 0.25 * budget_s / per_kmer  # k-mers one thread handles in a quarter of the budget
+
+    # one thread
+    s1 = _prefix_batch(ins, ioff, max(n_cal, share))
     F[:] = 0
     t0 = time.perf_counter()
-    oracle.insert(p, F, ins[:n_ins])
+    oracle.insert(p, F, *s1)
     t_ins = time.perf_counter() - t0
-    k_ins = max(0, n_ins - k + 1)
-    nrec = qoff.size - 1
-
-    def reads(kmers, starts=(0, nrec // 2)):
-        # whole reads from each start, up to the next start
-        take = []
-        bounds = list(starts) + [nrec]
-        for start, stop in zip(bounds[:-1], bounds[1:]):
-            r, got = start, 0
-            while r < stop and got < kmers // len(starts):
-                got += max(0, int(qoff[r + 1] - qoff[r]) - k + 1)
-                r += 1
-            take.append((start, r))
-        return take
-
-    take = reads(int(0.25 * budget_s / per_kmer))
-    t_q = 0.0
-    k_q = 0
-    for a, b in take:
-        s_, o_ = qs[int(qoff[a]):int(qoff[b])], qoff[a:b + 1] - qoff[a]
-        t0 = time.perf_counter()
-        oracle.query(p, F, s_, o_)
-        t_q += time.perf_counter() - t0
-        k_q += kmer_positions(o_, k)
+    k_ins = kmer_positions(s1[1], k)
+    q1 = cpu_query_sample(w, s1, share, 7001)
+    t0 = time.perf_counter()
+    oracle.query(p, F, *q1)
+    t_q = time.perf_counter() - t0
+    k_q = kmer_positions(q1[1], k)
     single = (k_ins + k_q) / (t_ins + t_q)
 
-    # every CPU: a larger sample, split over the threads
-    nt = host_cpu()["host_cpus"] or 1
-    n_ins_mt = int(min(ins.size, max(n_ins, nt * 0.25 * budget_s / per_kmer)))
-    pieces = _insert_pieces(ioff, n_ins_mt, nt, k)
-    filters = [p.empty() for _ in pieces]
-    for G in filters:
-        G[:] = 0  # touch the pages outside the timed region
-
-    def run_threads(fns):
-        th = [threading.Thread(target=fn) for fn in fns]
-        for t in th:
-            t.start()
-        for t in th:
-            t.join()
-
-    def or_slice(lo, hi):
-        for G in filters[1:]:
-            np.bitwise_or(filters[0][lo:hi], G[lo:hi], out=filters[0][lo:hi])
-
-    cut = np.linspace(0, p.nwords, nt + 1).astype(np.int64)
+    # every CPU, one shared filter
+    sm = _prefix_batch(ins, ioff, max(s1[0].size, nt * share))
+    qm = cpu_query_sample(w, sm, nt * share, 7101)
+    F[:] = 0
     t0 = time.perf_counter()
-    run_threads([lambda a=a, e=e, loc=loc, G=G: oracle.insert(p, G, ins[a:e], loc)
-                 for (a, e, loc), G in zip(pieces, filters)])
-    run_threads([lambda lo=int(lo), hi=int(hi): or_slice(lo, hi) for lo, hi in zip(cut[:-1], cut[1:])])
+    oracle.insert_parallel(p, F, *sm, threads=nt)
     t_ins_mt = time.perf_counter() - t0
-    Fm = filters[0]
-    k_ins_mt = kmer_positions(ioff[ioff <= n_ins_mt] if ioff[-1] <= n_ins_mt else
-                              np.concatenate((ioff[ioff < n_ins_mt], [n_ins_mt])), k)
-    del filters
-    q_kmers = min(int(nt * 0.25 * budget_s / per_kmer), kmer_positions(qoff, k))
-    take_mt = reads(q_kmers, starts=tuple(int(x) for x in np.linspace(0, nrec, 2 * nt, endpoint=False)))
-    parts = [(qs[int(qoff[a]):int(qoff[b])], qoff[a:b + 1] - qoff[a]) for a, b in take_mt if b > a]
+    k_ins_mt = kmer_positions(sm[1], k)
     t0 = time.perf_counter()
-    run_threads([lambda s_=s_, o_=o_: oracle.query(p, Fm, s_, o_) for s_, o_ in parts])
+    oracle.query_parallel(p, F, *qm, threads=nt)
     t_q_mt = time.perf_counter() - t0
-    k_q_mt = sum(kmer_positions(o_, k) for _, o_ in parts)
+    k_q_mt = kmer_positions(qm[1], k)
+    del F
     multi = (k_ins_mt + k_q_mt) / (t_ins_mt + t_q_mt)
     return {"value": multi, "unit": "k-mers/s", "cores": nt, "kind": "oracle", **host_cpu(),
             "single_thread_value": single,
-            "sample": "%d threads: %d k-mers inserted (first %d bases of the genome, %d pieces, filters OR-ed) + "
-                      "%d k-mers queried (%d reads), insert %.3g k-mers/s, query %.3g k-mers/s; one thread: %d "
-                      "k-mers inserted (first %d bases of contig 0) + %d queried, insert %.3g k-mers/s, "
-                      "query %.3g k-mers/s" % (
-                          nt, k_ins_mt, n_ins_mt, len(pieces), k_q_mt, sum(b - a for a, b in take_mt),
-                          k_ins_mt / t_ins_mt, k_q_mt / max(t_q_mt, 1e-9), k_ins, n_ins, k_q,
-                          k_ins / t_ins, k_q / max(t_q, 1e-9))}
+            "sample": "filter of the workload's size (%d bits, %.2f GiB) shared by all threads; %d threads: first %d "
+                      "bases of the genome inserted (%d k-mers, atomic ORs) + %d query reads (%d k-mers: the "
+                      "workload's negative reads of every class and as many positives drawn from the inserted "
+                      "bases), insert %.3g k-mers/s, query %.3g k-mers/s; one thread: %d k-mers inserted + %d "
+                      "queried, insert %.3g k-mers/s, query %.3g k-mers/s" % (
+                          p.nwords * 64, p.nwords * 8 / 2**30, nt, sm[0].size, k_ins_mt, qm[1].size - 1, k_q_mt,
+                          k_ins_mt / t_ins_mt, k_q_mt / max(t_q_mt, 1e-9), k_ins, k_q, k_ins / t_ins,
+                          k_q / max(t_q, 1e-9))}
+
+
+def stored_oracle(workload_name: str):
+    """The oracle's stored results for a workload (tests/golden/segment_counts.json,
+    written by tests/golden/segment_counts.py), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "segment_counts.json")
+    if not os.path.exists(path):
+        return None
+    return json.load(open(path)).get(workload_name)
 
 
 def stored_segments(workload_name: str, part: str, kmers: int):
@@ -253,33 +254,71 @@ def stored_segments(workload_name: str, part: str, kmers: int):
     return int(d["segments"])
 
 
-def run_probes(sizes_mib, copy_only=False, modes=None, quiet=False):
-    """Random shard-access and copy rates from libsbf_probe.so (include/sbf_probe.h)."""
+PROBE_NAMES = ["read", "rmw", "atomic4", "atomic1", "copy"]
+# in-flight depths compiled into the probe per shard size (include/sbf_probe.h)
+PROBE_DEPTHS = {32: (1, 4, 8, 16), 64: (1, 4, 8), 128: (1, 2, 4)}
+PROBE_WGS = (1, 2, 4, 8)
+
+
+def _probe_fn():
     import ctypes
 
     from paper_2606_24417_amd import build
 
     L = ctypes.CDLL(build.PROBE_LIB)
     fn = L.sbf_probe_random_access
-    fn.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
-                   ctypes.POINTER(ctypes.c_double)]
-    names = ["read32", "rmw32", "atomic4", "atomic1", "copy"]
+    fn.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    return fn
+
+
+def probe_once(mib, mode, shard_bytes=32, inflight=1, wgs_per_cu=4, ops=1 << 28):
+    """One random-access probe launch configuration: (rate per second, ms)."""
+    import ctypes
+
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    rc = _probe_fn()(int(mib) << 20, mode, shard_bytes, inflight, wgs_per_cu, ops, ctypes.byref(rate),
+                     ctypes.byref(ms))
+    if rc != 0:
+        raise SystemExit("probe failed rc=%d (mode %d, %d MiB, %d B, depth %d, %d WG/CU)" % (
+            rc, mode, mib, shard_bytes, inflight, wgs_per_cu))
+    return rate.value, ms.value
+
+
+def probe_ceiling(mib, mode, shard_bytes=32, ops=1 << 28):
+    """Best rate of random shard operations over the in-flight depths and
+    occupancies the probe offers: the ceiling a kernel doing the same
+    accesses could reach.  Returns (best, table of every setting)."""
+    table = []
+    for d in PROBE_DEPTHS[shard_bytes]:
+        for wg in PROBE_WGS:
+            rate, ms = probe_once(mib, mode, shard_bytes, d, wg, ops)
+            table.append({"inflight": d, "wgs_per_cu": wg, "G_per_s": round(rate / 1e9, 2), "ms": round(ms, 3)})
+    best = max(table, key=lambda r: r["G_per_s"])
+    return best, table
+
+
+def run_probes(sizes_mib, modes=(0, 1, 2, 3), shard_bytes=(32,), quiet=False):
+    """Random shard-access ceilings (include/sbf_probe.h) per buffer size."""
     out = []
-    if modes is None:
-        modes = [4] if copy_only else [0, 1, 2, 3, 4]
     for mib in sizes_mib:
-        row = {"buffer_mib": mib}
-        for mode in modes:
-            rate, ms = ctypes.c_double(), ctypes.c_double()
-            rc = fn(int(mib) << 20, mode, 1 << 26, ctypes.byref(rate), ctypes.byref(ms))
-            if rc != 0:
-                raise SystemExit("probe failed rc=%d (mode %d, %d MiB)" % (rc, mode, mib))
-            key = names[mode] + ("_GBps" if mode == 4 else "_Gops")
-            row[key] = round(rate.value / 1e9, 2)
-            row[names[mode] + "_ms"] = round(ms.value, 4)
-        out.append(row)
-        print(json.dumps(row), file=sys.stderr if quiet else sys.stdout, flush=True)
+        for sb in shard_bytes:
+            row = {"buffer_mib": mib, "shard_bytes": sb}
+            for mode in modes:
+                best, table = probe_ceiling(mib, mode, sb)
+                row[PROBE_NAMES[mode]] = {"best_G_per_s": best["G_per_s"], "inflight": best["inflight"],
+                                          "wgs_per_cu": best["wgs_per_cu"], "ms": best["ms"],
+                                          "sweep": [(r["inflight"], r["wgs_per_cu"], r["G_per_s"]) for r in table]}
+            out.append(row)
+            print(json.dumps(row), file=sys.stderr if quiet else sys.stdout, flush=True)
     return out
+
+
+def run_copy_probe(mib):
+    rate, ms = probe_once(mib, 4)
+    row = {"buffer_mib": mib, "copy_GBps": round(rate / 1e9, 1), "ms": round(ms, 4)}
+    print(json.dumps(row), flush=True)
+    return row
 
 
 VALU_OPS = ["add32", "mul32", "mad64", "shl64", "bitop3", "cmp64"]
@@ -707,7 +746,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="in_cache",
+    ap.add_argument("--workload", default="out_of_cache",
                     choices=["in_cache", "out_of_cache", "tiny", "batched", "served", "host", "sweep"])
     ap.add_argument("--sweep-points", type=int, default=0, help="sweep: only the first n (s,m,H) points")
     ap.add_argument("--staging-mib", type=int, default=0, help="host: chunk size of the host entry points")
@@ -717,6 +756,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="served: server execution slots")
     ap.add_argument("--window-us", type=int, default=0, help="served: batching window in microseconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-in-cache", action="store_true",
+                    help="out_of_cache: skip the in-cache workload reported as a second key")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the live roofline probes (random access out of cache, 32-bit add rate in cache)")
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")
@@ -742,16 +783,22 @@ def main():
 
     if args.probe:
         run_probes([2, 32, 256, 1024, 8192])
+        run_probes([8192], modes=(0, 1), shard_bytes=(64, 128))
+        for mib in (2, 32, 256, 8192):
+            run_copy_probe(mib)
         run_valu_probes()
         return
     if args.probe_valu:
         run_valu_probes()
         return
     if args.probe_copy_mib:
-        run_probes([args.probe_copy_mib], copy_only=True)
+        run_copy_probe(args.probe_copy_mib)
         return
     if args.probe_read_mib:
-        run_probes([args.probe_read_mib], modes=[0])
+        # one fixed setting, for counter calibration
+        rate, ms = probe_once(args.probe_read_mib, 0, 32, 8, 4)
+        print(json.dumps({"buffer_mib": args.probe_read_mib, "read_G_per_s": round(rate / 1e9, 2), "ms": ms,
+                          "ops": 1 << 28}), flush=True)
         return
 
     if args.workload == "batched":
@@ -767,12 +814,39 @@ def main():
         bench_sweep(args)
         return
 
+    res = measure(args, args.workload, with_cpu=not args.no_cpu_baseline)
+    if args.workload == "out_of_cache" and not args.no_in_cache:
+        # the in-cache workload as a second key of the same line
+        sub = measure(args, "in_cache", with_cpu=False)
+        res["in_cache"] = {key: sub[key] for key in (
+            "value", "ms_per_step", "config", "p50_batch_ms", "p99_batch_ms", "insert_kmers_per_s",
+            "query_kmers_per_s", "insert_ms_median", "query_ms_median", "query_present", "oracle_check",
+            "roofline", "roofline_other")}
+    print(json.dumps(res), flush=True)
+    if not all(r.get("oracle_check", {}).get("ok", True) for r in (res, res.get("in_cache", {}))):
+        sys.exit(1)
+
+
+def _sha256(a: np.ndarray) -> str:
+    h = hashlib.sha256()
+    step = 1 << 28
+    for i in range(0, a.size, step):
+        h.update(memoryview(np.ascontiguousarray(a[i:i + step])).cast("B"))
+    return h.hexdigest()
+
+
+def measure(args, name, with_cpu):
+    """One workload: W untimed and K timed steps (clear the filter, mark the
+    record starts of both batches, insert the genome, query the reads), with
+    HIP events around the insert and the query on torch's current stream, on
+    which the library launches its kernels.  After the timed steps the filter
+    and answers are checked against the oracle's stored digests."""
     import torch
 
     from paper_2606_24417_amd import Filter
 
     t_gen = time.perf_counter()
-    w = workload(args.workload)
+    w = workload(name)
     if args.bits:
         w["bits"] = args.bits
     t_gen = time.perf_counter() - t_gen
@@ -782,7 +856,7 @@ def main():
     n_ins_kmers = kmer_positions(ioff, k)
     n_q_kmers = kmer_positions(qoff, k)
     print("[bench] workload %s generated in %.1fs: insert %d bases (%d k-mers), query %d bases (%d k-mers)" % (
-        args.workload, t_gen, ins.size, n_ins_kmers, qs.size, n_q_kmers), file=sys.stderr, flush=True)
+        name, t_gen, ins.size, n_ins_kmers, qs.size, n_q_kmers), file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
     d_ins = torch.from_numpy(ins).to(dev)
@@ -798,11 +872,9 @@ def main():
     if args.launch:
         li, lq = (int(x) for x in args.launch.split(","))
         f.set_launch(li, lq)
-    tuned = None
     if args.autotune:
         report = f.autotune(d_ins, d_ioff, d_q, d_qoff)
         print(report, file=sys.stderr, flush=True)
-        tuned = f.get_launch()
     ins_starts = Filter.mark_record_starts(d_ioff, ins.size)
     q_starts = Filter.mark_record_starts(d_qoff, qs.size)
     torch.cuda.synchronize()
@@ -837,23 +909,46 @@ def main():
     q_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
     ms_per_step = wall * 1e3 / args.steps
 
-    # correctness spot check of this run: every positive read k-mer without an
-    # error is present and the negatives' FPR is small
+    # Check of this run, outside the timed region: the filter left by the last
+    # step and the answers of its query against the oracle's results for the
+    # whole workload, stored by tests/golden/segment_counts.py.
     ans = d_out.cpu().numpy()
-    n_q_valid = int(ans.sum())
+    n_q_valid = int(ans.sum(dtype=np.int64))
+    stored = stored_oracle(name)
+    check = {"ok": None, "note": "no stored oracle result for this workload"}
+    if stored and "oracle_answers" in stored and stored["query"]["bases"] == qs.size and not args.bits:
+        ans_ok = _sha256(ans) == stored["oracle_answers"]["sha256"]
+        bits_ok = _sha256(f.get_bits()) == stored["oracle_filter"]["sha256"]
+        check = {"ok": bool(ans_ok and bits_ok and n_q_valid == stored["oracle_answers"]["present"]),
+                 "present": n_q_valid, "oracle_present": stored["oracle_answers"]["present"],
+                 "answers_sha256_equal": ans_ok, "filter_sha256_equal": bits_ok}
+    del ans
+    print("[bench] %s oracle check: %s" % (name, json.dumps(check)), file=sys.stderr, flush=True)
 
     total_kmers = n_ins_kmers + n_q_kmers
     value = total_kmers / (ms_per_step * 1e-3)
     q_rate = n_q_kmers / (np.median(q_ms) * 1e-3)
     i_rate = n_ins_kmers / (np.median(ins_ms) * 1e-3)
-    # Roofline of the largest single kernel launch.  The insert is two launches
-    # of one kernel (store pass, then repair pass) unless it runs in atomic
-    # mode; the query is one launch.
+    # Roofline of the dominant work: the insert is two launches (store pass,
+    # then repair walk) unless it runs in atomic mode; the query is one.
     settings = f.get_launch()
     ins_launches = 1 if settings["insert_mode"] == 1 else 2
     q_kernel = {0: "query_lane_kernel", 1: "query_rolling_kernel (leader)", 2: "query_rolling_kernel (direct)"}[
         settings["query_mode"]] + "<31,28,16,4>"
-    in_cache = args.workload != "out_of_cache"
+    in_cache = name != "out_of_cache"
+
+    valu = None
+    if in_cache and not args.no_probe:
+        valu = round(valu_rate(SBF_PROBE_VALU_ADD32) * 64 / 1e12, 2)
+    probe = None
+    if not in_cache and not args.no_probe:
+        # ceilings of random 32-byte shard reads and read-modify-writes over an
+        # 8 GiB buffer (best over in-flight depth and occupancy), measured now
+        probe = {}
+        for mode in (0, 1):
+            best, table = probe_ceiling(8192, mode, 32)
+            probe[PROBE_NAMES[mode]] = best
+        print("[bench] random-access ceilings (8 GiB, 32 B): %s" % json.dumps(probe), file=sys.stderr, flush=True)
 
     def roofline(part, ms, kmers, launches):
         if in_cache:
@@ -862,7 +957,7 @@ def main():
             r = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT_TOPS, "unit": "TOP/s (int32)",
                  "frac": round(achieved / PEAK_INT_TOPS, 4), "ops_per_kmer": OPS_PER_KMER[part]}
         else:
-            nseg = stored_segments(args.workload, part, kmers)
+            nseg = stored_segments(name, part, kmers)
             seqs = w[part]
             if nseg is None:
                 r = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
@@ -872,8 +967,9 @@ def main():
                 nbytes = nseg * per_seg + seqs[0].size * (2 if part == "query" else 1)
                 achieved = nbytes / (ms * 1e-3) / 1e9
                 r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "segments": nseg}
-        r["traffic"] = counter_traffic(args.workload, part, kmers)
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "segments": nseg,
+                     "algorithmic_bytes": nbytes}
+        r["traffic"] = counter_traffic(name, part, kmers)
         if in_cache and valu is not None:
             # the same algorithmic ops against the 32-bit add rate measured now
             # on this GPU (simple 32-bit ops issue faster than one wave64
@@ -882,22 +978,18 @@ def main():
             r["valu_probe"] = {"add32_T_lane_ops_per_s": valu, "frac": round(r["achieved"] / valu, 4)}
         if probe is not None and r.get("segments"):
             # segments (one random 32-byte shard access each) per second against
-            # the probe's random read rate (query) or read-modify-write rate (insert)
+            # the probe's best random read rate (query) or read-modify-write
+            # rate (insert)
             seg_rate = r["segments"] / (ms * 1e-3)
-            peak = probe["read32_Gops" if part == "query" else "rmw32_Gops"] * 1e9
-            r["random_access"] = {"segments_per_s": seg_rate, "probe_peak_per_s": peak,
-                                  "probe": "read32" if part == "query" else "rmw32", "frac": round(seg_rate / peak, 4)}
+            best = probe["read" if part == "query" else "rmw"]
+            peak = best["G_per_s"] * 1e9
+            r["random_access"] = {"segments_per_s": seg_rate, "probe_ceiling_per_s": peak,
+                                  "probe": ("read" if part == "query" else "read-modify-write") + " 32 B",
+                                  "probe_setting": {"inflight": best["inflight"], "wgs_per_cu": best["wgs_per_cu"]},
+                                  "frac": round(seg_rate / peak, 4)}
         r["launches"] = launches
         r["kernel_ms"] = round(ms, 4)
         return r
-
-    valu = None
-    if in_cache and not args.no_probe:
-        valu = round(valu_rate(SBF_PROBE_VALU_ADD32) * 64 / 1e12, 2)
-    probe = None
-    if not in_cache and not args.no_probe:
-        # random 32-byte sector rates over an 8 GiB buffer, measured now on this GPU
-        probe = {r["buffer_mib"]: r for r in run_probes([8192], modes=[0, 1], quiet=True)}[8192]
 
     q_mean = float(np.mean(q_ms))
     i_mean = float(np.mean(ins_ms))
@@ -935,15 +1027,20 @@ def main():
         "insert_ms_median": round(float(np.median(ins_ms)), 4),
         "query_ms_median": round(float(np.median(q_ms)), 4),
         "query_present": n_q_valid,
+        "oracle_check": check,
         "settings": settings,
         "roofline": roof,
         "roofline_other": roof_other,
         "cpu_baseline": None,
     }
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w)
     f.close()
-    print(json.dumps(res), flush=True)
+    del d_ins, d_q, d_out, d_ioff, d_qoff, ins_starts, q_starts
+    torch.cuda.empty_cache()
+    if with_cpu:
+        t0 = time.perf_counter()
+        res["cpu_baseline"] = cpu_baseline(w)
+        print("[bench] cpu baseline in %.1fs" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    return res
 
 
 if __name__ == "__main__":

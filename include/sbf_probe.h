@@ -6,8 +6,10 @@
  * segment at a random place in the filter (Section "Data Layout": 256-bit
  * shards; Section "Speed-of-Light Analysis": DRAM pressure once the filter
  * outgrows the caches).  These probes measure how many such random shard
- * accesses per second the device sustains over a buffer of a given size, plus
- * a streaming copy of known size used to calibrate hardware byte counters.
+ * accesses per second the device sustains over a buffer of a given size, with
+ * many independent accesses in flight per lane and a sweep of occupancy, so
+ * that the best setting is a ceiling for the kernels; plus a streaming copy of
+ * known size used to calibrate hardware byte counters.
  */
 #ifndef SBF_PROBE_H
 #define SBF_PROBE_H
@@ -18,22 +20,31 @@
 extern "C" {
 #endif
 
-#define SBF_PROBE_READ32 0     /* read one random 32-byte shard (two 16-byte loads) */
-#define SBF_PROBE_RMW32 1      /* read a random shard, OR a bit, write it back (plain) */
-#define SBF_PROBE_ATOMIC4 2    /* four 64-bit atomic ORs on one random shard */
-#define SBF_PROBE_ATOMIC1 3    /* one 64-bit atomic OR on one random shard */
-#define SBF_PROBE_COPY 4       /* streaming copy of bytes/2 bytes within the buffer */
+#define SBF_PROBE_READ 0     /* read one random shard (16-byte loads) */
+#define SBF_PROBE_RMW 1      /* read a random shard, OR a bit, write it back (plain) */
+#define SBF_PROBE_ATOMIC4 2  /* four 64-bit atomic ORs on one random shard */
+#define SBF_PROBE_ATOMIC1 3  /* one 64-bit atomic OR on one random shard */
+#define SBF_PROBE_COPY 4     /* streaming copy of bytes/2 bytes within the buffer */
 
 /* Run probe `mode` over a device buffer of `bytes` bytes (a power of two,
  * 64 KiB .. 64 GiB; allocated, zeroed and freed by the call) on the current
- * device.  For the random modes, `ops` shard operations are issued (at
- * least 2^20); for SBF_PROBE_COPY, ops is ignored.  On success writes the
- * rate to *per_second (shard operations/s, or bytes moved/s counting read
- * plus write for the copy) and the mean kernel time to *ms, and returns 0;
- * returns -1 for bad arguments, -2 when the allocation fails, -3 on a HIP
- * error.  Each measurement is the mean of three launches after one warm-up
- * launch. */
-int sbf_probe_random_access(uint64_t bytes, int mode, uint64_t ops, double *per_second, double *ms);
+ * device.
+ *   shard_bytes: 32, 64 or 128 (the filter's shard of 4, 8 or 16 words);
+ *   inflight: shards each lane addresses before it uses any of them, so that
+ *     inflight * shard_bytes / 16 loads are in flight per lane: 1, 4, 8 or 16
+ *     for 32-byte shards, 1, 4 or 8 for 64, 1, 2 or 4 for 128;
+ *   wgs_per_cu: 256-lane workgroups launched per compute unit (1 .. 16), each
+ *     running its share of the operations (waves per SIMD = wgs_per_cu when
+ *     registers allow);
+ *   ops: shard operations to issue, at least 2^20 (rounded up to whole
+ *     batches of the grid).
+ * For SBF_PROBE_COPY only bytes is used.  On success writes the rate to
+ * *per_second (shard operations/s, or bytes moved/s counting read plus write
+ * for the copy) and the mean kernel time to *ms, and returns 0; returns -1 for
+ * bad arguments, -2 when the allocation fails, -3 on a HIP error.  Each
+ * measurement is the mean of three launches after one warm-up launch. */
+int sbf_probe_random_access(uint64_t bytes, int mode, uint32_t shard_bytes, uint32_t inflight, uint32_t wgs_per_cu,
+                            uint64_t ops, double *per_second, double *ms);
 
 /* Integer vector-ALU issue rates behind the in-cache roofline (Section
  * "Speed-of-Light Analysis": in cache the kernels are compute-bound).  Each

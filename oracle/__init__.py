@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
         L.orc_min_hash.restype = _u64
         L.orc_insert_records.argtypes = [_u32, _u32, _u32, _u32, _u32, _u64, _u64p, _u8p, _u64p, _u64]
         L.orc_insert_records.restype = None
+        L.orc_insert_records_shared.argtypes = L.orc_insert_records.argtypes
+        L.orc_insert_records_shared.restype = None
         L.orc_query_records.argtypes = [_u32, _u32, _u32, _u32, _u32, _u64, _u64p, _u8p, _u64p, _u64, _u8p]
         L.orc_query_records.restype = None
         L.orc_kmer_shards.argtypes = [_u32, _u32, _u64, _u8p, _u64, _u64p]
@@ -173,6 +175,79 @@ def insert(p: Params, F: np.ndarray, seq, offsets=None) -> np.ndarray:
     lib().orc_insert_records(p.k, p.s, p.m, p.H, p.shard_words, p.nshards, _p(F, _u64p),
                              _p(s, _u8p), _p(off, _u64p), off.size - 1)
     return F
+
+
+def pieces(off: np.ndarray, total: int, n: int, k: int):
+    """Split bases [0, total) of a record batch into at most n ranges whose
+    k-mer starts partition [0, total - k + 1): (a, b, e, local offsets), where
+    the range holds bases [a, e) with e = min(total, b + k - 1) and its record
+    starts as offsets local to a.  Every k-mer starting in [a, b) lies inside
+    the range, so a range inserts or answers exactly those k-mers."""
+    off = np.asarray(off, dtype=np.uint64)
+    cuts = np.unique(np.linspace(0, max(total - k + 1, 0), n + 1).astype(np.int64))
+    out = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        a, b = int(a), int(b)
+        e = min(total, b + k - 1)
+        inner = off[(off > a) & (off < e)].astype(np.int64) - a
+        loc = np.concatenate(([0], inner, [e - a])).astype(np.uint64)
+        out.append((a, b, e, loc))
+    return out
+
+
+def _threads(threads) -> int:
+    return max(1, int(threads or os.cpu_count() or 1))
+
+
+def insert_parallel(p: Params, F: np.ndarray, seq, offsets=None, threads: int | None = None) -> np.ndarray:
+    """insert() on several threads into the one filter F: the batch is cut
+    into k-1-overlapping pieces (pieces()) that insert with atomic ORs
+    (orc_insert_records_shared); the result equals insert()."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    s = _u8(seq)
+    off = _offsets(s, offsets)
+    assert F.dtype == np.uint64 and F.flags.c_contiguous and F.size == p.nwords
+    nt = _threads(threads)
+    L = lib()
+
+    def run(job):
+        a, _, e, loc = job
+        part = s[a:e]
+        L.orc_insert_records_shared(p.k, p.s, p.m, p.H, p.shard_words, p.nshards, _p(F, _u64p),
+                                    _p(part, _u8p), _p(loc, _u64p), loc.size - 1)
+
+    jobs = pieces(off, s.size, 4 * nt, p.k)
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(run, jobs))
+    return F
+
+
+def query_parallel(p: Params, F: np.ndarray, seq, offsets, threads: int | None = None) -> np.ndarray:
+    """query() of a record batch on several threads (answers per base
+    position, length offsets[-1]); equal to query(p, F, seq, offsets)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    s = _u8(seq)
+    off = _offsets(s, offsets)
+    F = np.ascontiguousarray(F)
+    assert F.dtype == np.uint64 and F.size == p.nwords
+    out = np.zeros(s.size, dtype=np.uint8)
+    nt = _threads(threads)
+    L = lib()
+
+    def run(job):
+        a, b, e, loc = job
+        part = s[a:e]
+        res = np.zeros(e - a, dtype=np.uint8)
+        L.orc_query_records(p.k, p.s, p.m, p.H, p.shard_words, p.nshards, _p(F, _u64p), _p(part, _u8p),
+                            _p(loc, _u64p), loc.size - 1, _p(res, _u8p))
+        out[a:b] = res[:b - a]
+
+    jobs = pieces(off, s.size, 4 * nt, p.k)
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(run, jobs))
+    return out
 
 
 def query(p: Params, F: np.ndarray, seq, offsets=None, per_base: bool | None = None) -> np.ndarray:

@@ -156,15 +156,26 @@ static uint64_t shard_of(const orc_params *p, uint64_t K)
     return orc_min_hash(K, p->k, p->m) & (p->nshards - 1ULL);
 }
 
+/* Set one bit of a filter word.  With `shared` the OR is atomic (relaxed), so
+ * that several threads may insert into one filter at once; OR is commutative
+ * and idempotent, so the result does not depend on their interleaving. */
+static void or_bit(uint64_t *word, uint64_t bit, int shared)
+{
+    if (shared)
+        __atomic_fetch_or(word, bit, __ATOMIC_RELAXED);
+    else
+        *word |= bit;
+}
+
 /* InsertKmer of Algorithm 1 for one valid packed k-mer. */
-void orc_insert_kmer(const orc_params *p, uint64_t *F, uint64_t K)
+static void insert_kmer(const orc_params *p, uint64_t *F, uint64_t K, int shared)
 {
     uint64_t shard = shard_of(p, K);
     uint64_t *words = F + shard * p->S;
     for (uint32_t i = 0; i + p->s <= p->k; i++) {
         uint64_t g = orc_hash_smer(orc_subwindow(K, p->k, p->s, i));
         for (uint32_t t = 0; t < p->H; t++)
-            words[orc_word_index(g, t, p->H, p->S)] |= 1ULL << orc_bit_address(g, t, p->H);
+            or_bit(&words[orc_word_index(g, t, p->H, p->S)], 1ULL << orc_bit_address(g, t, p->H), shared);
     }
 }
 
@@ -188,9 +199,9 @@ int orc_contains_kmer(const orc_params *p, const uint64_t *F, uint64_t K)
 /* Insert every valid k-mer of every record.  Record r is
  * seq[off[r] .. off[r+1]); k-mers never span two records (Section
  * "Sequence-Native Design": records are separated by an invalid symbol). */
-void orc_insert_records(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint32_t S,
-                        uint64_t nshards, uint64_t *F, const unsigned char *seq,
-                        const uint64_t *off, uint64_t nrec)
+static void insert_records(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint32_t S,
+                           uint64_t nshards, uint64_t *F, const unsigned char *seq,
+                           const uint64_t *off, uint64_t nrec, int shared)
 {
     orc_params p = {k, s, m, H, S, nshards};
     for (uint64_t r = 0; r < nrec; r++) {
@@ -198,9 +209,25 @@ void orc_insert_records(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint32_t
         for (uint64_t i = a; i + k <= b; i++) {
             uint64_t K;
             if (orc_pack(seq + i, k, &K))
-                orc_insert_kmer(&p, F, K);
+                insert_kmer(&p, F, K, shared);
         }
     }
+}
+
+void orc_insert_records(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint32_t S,
+                        uint64_t nshards, uint64_t *F, const unsigned char *seq,
+                        const uint64_t *off, uint64_t nrec)
+{
+    insert_records(k, s, m, H, S, nshards, F, seq, off, nrec, 0);
+}
+
+/* As orc_insert_records, with atomic ORs: threads may insert different
+ * records (or k-1-overlapping pieces of one) into one filter concurrently. */
+void orc_insert_records_shared(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint32_t S,
+                               uint64_t nshards, uint64_t *F, const unsigned char *seq,
+                               const uint64_t *off, uint64_t nrec)
+{
+    insert_records(k, s, m, H, S, nshards, F, seq, off, nrec, 1);
 }
 
 /* Query every k-mer position.  out is indexed by base position: out[i] is the

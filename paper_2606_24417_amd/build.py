@@ -32,20 +32,44 @@ def hipcc() -> str:
     return path if os.path.exists(path) else "hipcc"
 
 
-def _compile(out: str, sources, verbose: bool) -> str:
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-o", tmp]
-    cmd += [os.path.join(CSRC, s) for s in sources]
+def _run(cmd, verbose: bool, what: str) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     text = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
         sys.stderr.write(text + "\n")
-        raise RuntimeError("hipcc failed building %s" % os.path.basename(out))
+        raise RuntimeError("hipcc failed building %s" % what)
     if verbose and text.strip():
         print(text)
-    os.replace(tmp, out)
+
+
+def _compile(out: str, sources, verbose: bool) -> str:
+    """Compile each source to an object file (in parallel), then link the
+    shared library; every step writes temporary files first."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    tag = "%d" % os.getpid()
+    inc = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+    objs = [os.path.join(CSRC, os.path.splitext(src)[0] + ".o.tmp" + tag) for src in sources]
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+
+    def one(i):
+        _run([hipcc()] + flags + inc + ["-c", "-o", objs[i], os.path.join(CSRC, sources[i])], verbose,
+             os.path.basename(out))
+
+    try:
+        workers = max(1, min(len(sources), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1)))
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(one, range(len(sources))))
+        tmp = out + ".tmp" + tag
+        _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs, verbose,
+             os.path.basename(out))
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return out
 
 

@@ -8,7 +8,6 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kIters = 64;
 
 __device__ __forceinline__ uint64_t scramble(uint64_t x) {
   // MurmurHash3 64-bit finaliser: spreads thread/iteration ids over the buffer
@@ -20,34 +19,80 @@ __device__ __forceinline__ uint64_t scramble(uint64_t x) {
   return x;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void random_shards(uint64_t *__restrict__ buf, uint64_t shard_mask,
-                                                        uint64_t seed, uint64_t *__restrict__ sink) {
+// Random shard accesses with many memory operations in flight per lane: each
+// lane draws `D` independent shard indices, issues every load of the batch
+// (D shards of SB bytes = D * SB/16 16-byte loads) before it uses any of them,
+// then consumes them (read: fold into a checksum; read-modify-write: OR one
+// bit and store the shard back; atomics: fire-and-forget 64-bit atomic ORs).
+// The grid is num_CUs * wgs_per_cu workgroups that each run `batches` batches,
+// so occupancy (waves per SIMD) is a sweep parameter of the caller.  The
+// register budget allows two waves per SIMD, so that the compiler keeps every
+// load of a batch in its own registers instead of reusing them (which would
+// serialise the loads on waits).
+template <int MODE, int SB, int D>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void random_shards(uint64_t *__restrict__ buf, uint64_t shard_mask,
+                                                        uint64_t seed, uint32_t batches,
+                                                        uint64_t *__restrict__ sink) {
+  constexpr int C = SB / 16;  // 16-byte chunks per shard
   const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t nthreads = (uint64_t)gridDim.x * kBlock;
   uint64_t acc = 0;
-  for (int i = 0; i < kIters; ++i) {
-    const uint64_t h = scramble(tid * 0x9E3779B97F4A7C15ull + (uint64_t)i + seed);
-    uint64_t *p = buf + 4ull * (h & shard_mask);
-    const uint64_t bit = 1ull << (h >> 58);
-    if constexpr (MODE == SBF_PROBE_READ32) {
-      const uint4 *q = reinterpret_cast<const uint4 *>(p);
-      const uint4 a = q[0], b = q[1];
-      acc ^= (uint64_t)(a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w);
-    } else if constexpr (MODE == SBF_PROBE_RMW32) {
-      uint4 *q = reinterpret_cast<uint4 *>(p);
-      uint4 a = q[0], b = q[1];
-      a.x |= (uint32_t)bit;
-      b.w |= (uint32_t)(bit >> 32);
-      q[0] = a;
-      q[1] = b;
-    } else if constexpr (MODE == SBF_PROBE_ATOMIC4) {
+  for (uint32_t it = 0; it < batches; ++it) {
+    uint64_t idx[D];
+    uint64_t bit[D];
 #pragma unroll
-      for (int w = 0; w < 4; ++w) __hip_atomic_fetch_or(p + w, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int d = 0; d < D; ++d) {
+      const uint64_t op = ((uint64_t)it * nthreads + tid) * D + (uint64_t)d;
+      const uint64_t h = scramble(op * 0x9E3779B97F4A7C15ull + seed);
+      idx[d] = h & shard_mask;
+      bit[d] = 1ull << (h >> 58);
+    }
+    if constexpr (MODE == SBF_PROBE_READ || MODE == SBF_PROBE_RMW) {
+      uint4 v[D][C];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(buf + idx[d] * (SB / 8));
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[d][c] = q[c];
+      }
+      // Every load of the batch is issued before the first wait: the barrier
+      // keeps the machine scheduler from moving uses up between the loads, and
+      // the empty asm statements (which stay below the barrier) keep the IR
+      // optimiser from folding loaded values early.
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int c = 0; c < C; ++c) asm volatile("" : "+v"(v[d][c].x), "+v"(v[d][c].y), "+v"(v[d][c].z), "+v"(v[d][c].w));
+      if constexpr (MODE == SBF_PROBE_READ) {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc ^= (uint64_t)(v[d][c].x ^ v[d][c].y ^ v[d][c].z ^ v[d][c].w) + (uint64_t)c;
+      } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          v[d][0].x |= (uint32_t)bit[d];
+          v[d][C - 1].w |= (uint32_t)(bit[d] >> 32);
+          uint4 *q = reinterpret_cast<uint4 *>(buf + idx[d] * (SB / 8));
+#pragma unroll
+          for (int c = 0; c < C; ++c) q[c] = v[d][c];
+        }
+      }
     } else {
-      __hip_atomic_fetch_or(p, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        uint64_t *p = buf + idx[d] * (SB / 8);
+        if constexpr (MODE == SBF_PROBE_ATOMIC4) {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) __hip_atomic_fetch_or(p + w, bit[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          __hip_atomic_fetch_or(p, bit[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
     }
   }
-  if (MODE == SBF_PROBE_READ32 && acc == 0x5bd1e995ull) sink[0] = acc;  // keeps the loads
+  if (MODE == SBF_PROBE_READ && acc == 0x5bd1e995ull) sink[0] = acc;  // keeps the loads
 }
 
 __global__ __launch_bounds__(kBlock) void stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
@@ -56,30 +101,48 @@ __global__ __launch_bounds__(kBlock) void stream_copy(const uint4 *__restrict__ 
     dst[i] = src[i];
 }
 
-hipError_t launch(int mode, uint64_t *buf, uint64_t bytes, uint64_t ops, uint64_t seed, uint64_t *sink) {
+// In-flight depths compiled per shard size: at most 32 loads of 16 bytes
+// (128 registers of data) per lane.
+bool depth_supported(uint32_t sb, uint32_t d) {
+  switch (sb) {
+    case 32: return d == 1 || d == 4 || d == 8 || d == 16;
+    case 64: return d == 1 || d == 4 || d == 8;
+    case 128: return d == 1 || d == 2 || d == 4;
+    default: return false;
+  }
+}
+
+template <int MODE>
+hipError_t launch_random(uint64_t *buf, uint64_t bytes, uint32_t sb, uint32_t d, unsigned grid, uint32_t batches,
+                         uint64_t seed, uint64_t *sink) {
+  const uint64_t mask = bytes / sb - 1;
+#define SBF_PROBE_CASE(SB_, D_)                                                                              \
+  if (sb == SB_ && d == D_) {                                                                                \
+    hipLaunchKernelGGL((random_shards<MODE, SB_, D_>), dim3(grid), dim3(kBlock), 0, 0, buf, mask, seed, batches, \
+                       sink);                                                                                \
+    return hipGetLastError();                                                                                \
+  }
+  SBF_PROBE_CASE(32, 1) SBF_PROBE_CASE(32, 4) SBF_PROBE_CASE(32, 8) SBF_PROBE_CASE(32, 16)
+  SBF_PROBE_CASE(64, 1) SBF_PROBE_CASE(64, 4) SBF_PROBE_CASE(64, 8)
+  SBF_PROBE_CASE(128, 1) SBF_PROBE_CASE(128, 2) SBF_PROBE_CASE(128, 4)
+#undef SBF_PROBE_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch(int mode, uint64_t *buf, uint64_t bytes, uint32_t sb, uint32_t d, unsigned grid, uint32_t batches,
+                  uint64_t seed, uint64_t *sink) {
   if (mode == SBF_PROBE_COPY) {
     const uint64_t n = bytes / 2 / 16;
     hipLaunchKernelGGL(stream_copy, dim3(8192), dim3(kBlock), 0, 0, (const uint4 *)buf,
                        (uint4 *)(buf + bytes / 2 / 8), n);
     return hipGetLastError();
   }
-  const uint64_t mask = bytes / 32 - 1;
-  const unsigned grid = (unsigned)(ops / ((uint64_t)kBlock * kIters));
   switch (mode) {
-    case SBF_PROBE_READ32:
-      hipLaunchKernelGGL(random_shards<SBF_PROBE_READ32>, dim3(grid), dim3(kBlock), 0, 0, buf, mask, seed, sink);
-      break;
-    case SBF_PROBE_RMW32:
-      hipLaunchKernelGGL(random_shards<SBF_PROBE_RMW32>, dim3(grid), dim3(kBlock), 0, 0, buf, mask, seed, sink);
-      break;
-    case SBF_PROBE_ATOMIC4:
-      hipLaunchKernelGGL(random_shards<SBF_PROBE_ATOMIC4>, dim3(grid), dim3(kBlock), 0, 0, buf, mask, seed, sink);
-      break;
-    default:
-      hipLaunchKernelGGL(random_shards<SBF_PROBE_ATOMIC1>, dim3(grid), dim3(kBlock), 0, 0, buf, mask, seed, sink);
-      break;
+    case SBF_PROBE_READ: return launch_random<SBF_PROBE_READ>(buf, bytes, sb, d, grid, batches, seed, sink);
+    case SBF_PROBE_RMW: return launch_random<SBF_PROBE_RMW>(buf, bytes, sb, d, grid, batches, seed, sink);
+    case SBF_PROBE_ATOMIC4: return launch_random<SBF_PROBE_ATOMIC4>(buf, bytes, sb, d, grid, batches, seed, sink);
+    default: return launch_random<SBF_PROBE_ATOMIC1>(buf, bytes, sb, d, grid, batches, seed, sink);
   }
-  return hipGetLastError();
 }
 
 // Integer VALU issue-rate probe: eight independent chains of one instruction
@@ -167,13 +230,22 @@ extern "C" int sbf_probe_valu(int op, double *wave_instr_per_second, double *ms)
   return rc;
 }
 
-extern "C" int sbf_probe_random_access(uint64_t bytes, int mode, uint64_t ops, double *per_second, double *ms) {
-  if (!per_second || !ms || mode < SBF_PROBE_READ32 || mode > SBF_PROBE_COPY) return -1;
+extern "C" int sbf_probe_random_access(uint64_t bytes, int mode, uint32_t shard_bytes, uint32_t inflight,
+                                       uint32_t wgs_per_cu, uint64_t ops, double *per_second, double *ms) {
+  if (!per_second || !ms || mode < SBF_PROBE_READ || mode > SBF_PROBE_COPY) return -1;
   if (bytes < (1ull << 16) || bytes > (1ull << 36) || (bytes & (bytes - 1))) return -1;
-  const uint64_t chunk = (uint64_t)kBlock * kIters;
+  if (mode != SBF_PROBE_COPY && (!depth_supported(shard_bytes, inflight) || wgs_per_cu < 1 || wgs_per_cu > 16))
+    return -1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return -3;
+  const unsigned grid = (unsigned)cus * wgs_per_cu;
+  const uint64_t per_batch = (uint64_t)grid * kBlock * (mode == SBF_PROBE_COPY ? 1 : inflight);
   if (ops < (1ull << 20)) ops = 1ull << 20;
-  ops = (ops + chunk - 1) / chunk * chunk;
-  if (ops / chunk > 0x7fffffffull) return -1;
+  const uint64_t nb = (ops + per_batch - 1) / per_batch;
+  if (nb > 0xffffffffull) return -1;
+  const uint32_t batches = (uint32_t)nb;
   uint64_t *buf = nullptr, *sink = nullptr;
   if (hipMalloc((void **)&buf, bytes) != hipSuccess) return -2;
   if (hipMalloc((void **)&sink, 64) != hipSuccess) {
@@ -184,18 +256,20 @@ extern "C" int sbf_probe_random_access(uint64_t bytes, int mode, uint64_t ops, d
   hipEvent_t a = nullptr, b = nullptr;
   float t = 0.f;
   if (hipMemset(buf, 0, bytes) != hipSuccess || hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
-      launch(mode, buf, bytes, ops, 1, sink) != hipSuccess || hipEventRecord(a, 0) != hipSuccess) {
+      launch(mode, buf, bytes, shard_bytes, inflight, grid, batches, 1, sink) != hipSuccess ||
+      hipEventRecord(a, 0) != hipSuccess) {
     rc = -3;
   } else {
     for (int r = 0; r < 3 && rc == 0; ++r)
-      if (launch(mode, buf, bytes, ops, 7 + r, sink) != hipSuccess) rc = -3;
+      if (launch(mode, buf, bytes, shard_bytes, inflight, grid, batches, 7 + r, sink) != hipSuccess) rc = -3;
     if (rc == 0 && (hipEventRecord(b, 0) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
                     hipEventElapsedTime(&t, a, b) != hipSuccess))
       rc = -3;
   }
   if (rc == 0) {
     *ms = t / 3.0;
-    const double work = mode == SBF_PROBE_COPY ? (double)(bytes / 2 / 16 * 16) * 2.0 : (double)ops;
+    const double work =
+        mode == SBF_PROBE_COPY ? (double)(bytes / 2 / 16 * 16) * 2.0 : (double)per_batch * (double)batches;
     *per_second = work / (*ms * 1e-3);
   }
   if (a) (void)hipEventDestroy(a);

@@ -12,7 +12,9 @@ available here:
   substitutions), negatives are fresh background sequence.
 
 Sequences are ``uint8`` ASCII arrays; record batches carry ``uint64`` offsets
-with ``nrec + 1`` entries (record r is ``seq[off[r]:off[r+1]]``).
+with ``nrec + 1`` entries (record r is ``seq[off[r]:off[r+1]]``).  A query
+batch's ``read_classes`` lists (first positive record, end, first negative
+record, end) for each read class (short and long reads).
 """
 
 from __future__ import annotations
@@ -211,7 +213,7 @@ def tiny_workload():
                      (neg, np.array([0, neg.size], dtype=np.uint64)))
     return dict(name="tiny: 1 Mbp into 2^24 bits", k=31, s=28, m=16, H=4, bits=1 << 24,
                 insert=(ins, np.array([0, ins.size], dtype=np.uint64)), query=(q, qoff),
-                n_pos_records=1)
+                n_pos_records=1, read_classes=[(0, 1, 1, 2)])
 
 
 def in_cache_workload(scale: float = 1.0):
@@ -224,7 +226,8 @@ def in_cache_workload(scale: float = 1.0):
     neg = random_reads(nreads, 150, 203)
     q = concat(pos, neg)
     return dict(name="in-cache: 100 Mbp genome, 2M x 150 bp reads", k=31, s=28, m=16, H=4,
-                bits=16 * int(g[1][-1]), insert=g, query=q, n_pos_records=nreads)
+                bits=16 * int(g[1][-1]), insert=g, query=q, n_pos_records=nreads,
+                read_classes=[(0, nreads, nreads, 2 * nreads)])
 
 
 def out_of_cache_contigs(seed=301, total=3_000_000_000):
@@ -252,7 +255,9 @@ def out_of_cache_workload(scale: float = 1.0):
     lneg = random_reads(nlong, llen[nlong:], 305)
     q = concat(pos, neg, lpos, lneg)
     return dict(name="out-of-cache: 3 Gbp genome, 10M x 150 bp + 100k long reads", k=31, s=28,
-                m=16, H=4, bits=16 * total, insert=g, query=q)
+                m=16, H=4, bits=16 * total, insert=g, query=q,
+                read_classes=[(0, nshort, nshort, 2 * nshort),
+                              (2 * nshort, 2 * nshort + nlong, 2 * nshort + nlong, 2 * nshort + 2 * nlong)])
 
 
 def batched_workload(scale: float = 1.0):

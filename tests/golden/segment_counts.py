@@ -1,14 +1,24 @@
-"""Writes segment_counts.json next to this file: for each benchmark workload,
-the number of super-k-mer segments (maximal runs of consecutive valid k-mers
-of one record with one minimizer shard, Section "Minimizers and Super-k-mers")
-of its insert batch and its query batch, counted by the oracle over every
-record.  Each segment costs one shard access on the insert (read-modify-write)
-and query (read) paths, so these counts are the algorithmic memory traffic of
-the out-of-cache roofline.
+"""Writes segment_counts.json next to this file.  For each benchmark workload:
 
-    python tests/golden/segment_counts.py [workload ...]   (default: out_of_cache in_cache)
+* the number of super-k-mer segments (maximal runs of consecutive valid k-mers
+  of one record with one minimizer shard, Section "Minimizers and
+  Super-k-mers") of its insert batch and its query batch, counted by the
+  oracle over every record.  Each segment costs one shard access on the
+  insert (read-modify-write) and query (read) paths, so these counts are the
+  algorithmic memory traffic of the out-of-cache roofline;
+* the oracle's filter after inserting the whole insert batch (Algorithm 1)
+  and its answers to the whole query batch (Algorithm 2), as SHA-256 digests
+  of the little-endian words and of the answer bytes, whole and per block
+  (2^23 words = 64 MiB of filter, 2^26 answer bytes), with the number of set
+  bits and of k-mers answered present.  The full-size GPU tests compare the
+  GPU's filter and answers with these digests, and bench.py compares its
+  answer count with the stored one.
 
-Calls only oracle/ and synth/.
+    python tests/golden/segment_counts.py [workload ...]
+        (default: tiny in_cache out_of_cache batched)
+
+Calls only oracle/ and synth/; the oracle runs on every CPU (threads over
+k-1-overlapping pieces, atomic ORs into one filter).
 """
 
 from __future__ import annotations
@@ -29,6 +39,27 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 OUT = os.path.join(HERE, "segment_counts.json")
+FILTER_BLOCK_WORDS = 1 << 23
+ANSWER_BLOCK_BYTES = 1 << 26
+WORKLOADS = {"in_cache": synth.in_cache_workload, "out_of_cache": synth.out_of_cache_workload,
+             "tiny": synth.tiny_workload, "batched": synth.batched_workload}
+
+
+def digests(a: np.ndarray, block: int):
+    """SHA-256 of the array's bytes (little-endian), whole and per block of
+    `block` elements."""
+    import hashlib
+
+    a = np.ascontiguousarray(a)
+    if a.dtype.byteorder == ">":
+        a = a.byteswap().view(a.dtype.newbyteorder("<"))
+    whole = hashlib.sha256()
+    blocks = []
+    for i in range(0, a.size, block):
+        b = memoryview(a[i:i + block]).cast("B")
+        whole.update(b)
+        blocks.append(hashlib.sha256(b).hexdigest())
+    return whole.hexdigest(), blocks
 
 
 def kmer_positions(off: np.ndarray, k: int) -> int:
@@ -49,7 +80,7 @@ def count(p, batch, parts: int = 64) -> int:
     for a, b in zip(cuts[:-1], cuts[1:]):
         lo, hi = int(off[a]), int(off[b])
         jobs.append((seq[lo:hi], off[a:b + 1] - off[a]))
-    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         return int(sum(ex.map(lambda j: oracle.count_segments(p, j[0], j[1]), jobs)))
 
 
@@ -57,23 +88,35 @@ def main(names):
     res = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         t0 = time.perf_counter()
-        w = {"in_cache": synth.in_cache_workload, "out_of_cache": synth.out_of_cache_workload,
-             "tiny": synth.tiny_workload}[name]()
+        w = WORKLOADS[name]()
         p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
-        entry = {"workload": w["name"], "k": w["k"], "m": w["m"], "filter_bits_requested": int(w["bits"]),
-                 "nshards": int(p.nshards)}
+        entry = {"workload": w["name"], "k": w["k"], "s": w["s"], "m": w["m"], "H": w["H"],
+                 "filter_bits_requested": int(w["bits"]), "nshards": int(p.nshards)}
         for part in ("insert", "query"):
             seq, off = w[part]
             entry[part] = {"bases": int(seq.size), "kmers": kmer_positions(off, w["k"]),
                            "segments": count(p, (seq, off))}
             entry[part]["segments_per_kmer"] = entry[part]["segments"] / max(1, entry[part]["kmers"])
+        print(name, "segments %.0fs" % (time.perf_counter() - t0), flush=True)
+        F = oracle.insert_parallel(p, p.empty(), *w["insert"])
+        whole, blocks = digests(F, FILTER_BLOCK_WORDS)
+        entry["oracle_filter"] = {"words": int(F.size), "set_bits": int(np.bitwise_count(F).sum(dtype=np.int64)),
+                                  "sha256": whole, "block_words": FILTER_BLOCK_WORDS, "block_sha256": blocks}
+        print(name, "filter %.0fs" % (time.perf_counter() - t0), flush=True)
+        ans = oracle.query_parallel(p, F, *w["query"])
+        del F
+        whole, blocks = digests(ans, ANSWER_BLOCK_BYTES)
+        entry["oracle_answers"] = {"bytes": int(ans.size), "present": int(ans.sum(dtype=np.int64)),
+                                   "sha256": whole, "block_bytes": ANSWER_BLOCK_BYTES, "block_sha256": blocks}
+        del ans
         res[name] = entry
-        print(name, json.dumps(entry), "%.0fs" % (time.perf_counter() - t0), flush=True)
+        print(name, json.dumps({k: v for k, v in entry.items() if not k.startswith("oracle")}),
+              "present", entry["oracle_answers"]["present"], "%.0fs" % (time.perf_counter() - t0), flush=True)
         del w
-    with open(OUT, "w") as f:
-        json.dump(res, f, indent=1, sort_keys=True)
-        f.write("\n")
+        with open(OUT, "w") as f:
+            json.dump(res, f, indent=1, sort_keys=True)
+            f.write("\n")
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["out_of_cache", "in_cache"])
+    main(sys.argv[1:] or ["tiny", "in_cache", "out_of_cache", "batched"])

@@ -112,12 +112,18 @@ def test_probe_library_exports_its_header():
     assert v(0, None, None) == -1
     # argument checks happen before any device call
     fn = L.sbf_probe_random_access
-    fn.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
-                   ctypes.POINTER(ctypes.c_double)]
+    fn.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     a, b = ctypes.c_double(), ctypes.c_double()
-    assert fn(3 << 20, 0, 1 << 20, ctypes.byref(a), ctypes.byref(b)) == -1  # not a power of two
-    assert fn(1 << 20, 9, 1 << 20, ctypes.byref(a), ctypes.byref(b)) == -1  # bad mode
-    assert fn(1 << 20, 0, 1 << 20, None, None) == -1
+    ra, rb = ctypes.byref(a), ctypes.byref(b)
+    assert fn(3 << 20, 0, 32, 8, 4, 1 << 20, ra, rb) == -1  # not a power of two
+    assert fn(1 << 20, 9, 32, 8, 4, 1 << 20, ra, rb) == -1  # bad mode
+    assert fn(1 << 20, 0, 32, 8, 4, 1 << 20, None, None) == -1
+    assert fn(1 << 20, 0, 48, 8, 4, 1 << 20, ra, rb) == -1  # shard size
+    assert fn(1 << 20, 1, 32, 3, 4, 1 << 20, ra, rb) == -1  # in-flight depth not compiled
+    assert fn(1 << 20, 1, 128, 8, 4, 1 << 20, ra, rb) == -1
+    assert fn(1 << 20, 0, 32, 8, 0, 1 << 20, ra, rb) == -1  # workgroups per CU
+    assert fn(1 << 20, 0, 32, 8, 17, 1 << 20, ra, rb) == -1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -27,21 +27,30 @@ def test_valid_kmers_all_valid_equals_positions():
     assert bench.valid_kmers(seq, off, 31) == bench.kmer_positions(off, 31) == (500 - 10 - 30) + (500 - 30)
 
 
-def test_parallel_baseline_pieces_equal_one_insert():
-    """The CPU baseline's parallel insert (pieces with k-1 overlap and their
-    record starts, filters OR-ed) builds the filter of one serial insert."""
+def test_cpu_baseline_sample_batches():
+    """The CPU baseline's genome prefix keeps whole records and clips the last
+    one; its query sample takes every read class of the workload, negatives
+    from the workload's own negative reads and positives from the prefix (all
+    of their error-free k-mers are then in the prefix's filter)."""
     import oracle
+    import synth
 
-    rng = np.random.default_rng(3)
-    ins = rng.choice(np.frombuffer(b"ACGTN", dtype=np.uint8), size=120_000,
-                     p=[.24, .24, .24, .24, .04]).astype(np.uint8)
-    ioff = np.array([0, 1000, 1010, 50_000, 50_030, 90_000, 120_000], dtype=np.uint64)
-    p = oracle.Params(31, 28, 16, 4, 1 << 20)
-    for total in (120_000, 61_237):
-        clip = ioff[ioff <= total] if ioff[-1] <= total else np.concatenate((ioff[ioff < total], [total]))
-        want = oracle.insert(p, p.empty(), ins[:total], clip.astype(np.uint64))
-        for n in (1, 3, 16):
-            got = p.empty()
-            for a, e, loc in bench._insert_pieces(ioff, total, n, 31):
-                got |= oracle.insert(p, p.empty(), ins[a:e], loc)
-            assert np.array_equal(got, want), (total, n)
+    seq = np.frombuffer(b"ACGT" * 3000, dtype=np.uint8)
+    off = np.array([0, 100, 5000, 12000], dtype=np.uint64)
+    for n, want in ((50, [0, 50]), (100, [0, 100]), (101, [0, 100, 101]), (7000, [0, 100, 5000, 7000]),
+                    (20000, [0, 100, 5000, 12000])):
+        s, o = bench._prefix_batch(seq, off, n)
+        assert s.size == min(n, 12000) and o.tolist() == want
+    w = synth.tiny_workload()
+    pre = bench._prefix_batch(*w["insert"], 300_000)
+    q, qoff = bench.cpu_query_sample(w, pre, 100_000, 5)
+    assert abs(bench.kmer_positions(qoff, 31) - 100_000) < 1000
+    lens = np.diff(qoff.astype(np.int64))
+    assert lens.size == 2
+    p = oracle.Params(31, 28, 16, 4, 1 << 24)
+    F = oracle.insert(p, p.empty(), *pre)
+    ans = oracle.query(p, F, q, qoff)
+    pos = ans[:int(qoff[1])]
+    assert pos[:int(qoff[1]) - 30].mean() > 0.5   # positives drawn from the prefix (1% substitutions)
+    neg_start = int(w["query"][1][1])
+    assert np.array_equal(q[int(qoff[1]):], w["query"][0][neg_start:neg_start + int(lens[1])])

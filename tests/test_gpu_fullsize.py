@@ -1,19 +1,34 @@
 """Full-size GPU checks in the launch configuration bench.py times.
 
-In-cache workload (100 Mbp genome at 16 bits per k-mer, 2M reads): the whole
-filter is compared with the oracle's, and the answers of sampled reads.
-Out-of-cache workload (3 Gbp genome into 8 GiB, 10.1M reads): the oracle
-checks a sampled genome slice inserted alone at full filter geometry, the
-answers of sampled reads against the GPU's own filter, and the properties
-that hold at any size (every inserted k-mer is present; the sampled slice's
-bits are a subset of the full filter).
+Every filter word and every answer byte is compared with the oracle:
+
+* in-cache workload (100 Mbp genome at 16 bits per k-mer, 2M reads): the
+  oracle runs here, on every CPU (threads over k-1-overlapping pieces, atomic
+  ORs into one filter), and both results are compared element by element;
+* out-of-cache workload (3 Gbp genome into 8 GiB, 10.1M reads) and batched
+  workload (2M log-normal reads inserted and 2M queried through one HIP
+  graph): the GPU's filter and answers are compared with the SHA-256 digests
+  of the oracle's, per 64 MiB block, stored by tests/golden/segment_counts.py
+  (which calls only the oracle and the input generator);
+* a reduced batched workload (5% of the reads) through the graph against the
+  oracle run here.
+
+Properties that hold at any size are checked as well: every inserted k-mer is
+present, and false positives on random reads match the prediction from the
+filter's own sector popcounts.
 """
+
+import hashlib
+import json
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from conftest import golden
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -40,24 +55,42 @@ def off_dev(off):
     return torch.from_numpy(off.astype(np.uint64).view(np.int64)).cuda()
 
 
+def stored(name):
+    return json.load(open(golden("segment_counts.json")))[name]
+
+
+def block_digests(a: np.ndarray, block: int):
+    """SHA-256 per block of `block` elements (threads; hashlib releases the
+    interpreter lock on large buffers)."""
+    a = np.ascontiguousarray(a)
+    starts = range(0, a.size, block)
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda i: hashlib.sha256(memoryview(a[i:i + block]).cast("B")).hexdigest(), starts))
+
+
+def check_against_stored(name, bits, ans):
+    """Filter words and answer bytes against the oracle's stored digests; on a
+    mismatch, name the blocks that differ."""
+    d = stored(name)
+    fb = d["oracle_filter"]["block_words"]
+    got = block_digests(bits, fb)
+    bad = [i for i, (x, y) in enumerate(zip(got, d["oracle_filter"]["block_sha256"])) if x != y]
+    assert bits.size == d["oracle_filter"]["words"] and not bad, \
+        "filter differs from the oracle's in %d of %d blocks of %d words (first: %s)" % (
+            len(bad), len(got), fb, bad[:8])
+    assert int(np.bitwise_count(bits).sum(dtype=np.int64)) == d["oracle_filter"]["set_bits"]
+    ab = d["oracle_answers"]["block_bytes"]
+    got = block_digests(ans, ab)
+    bad = [i for i, (x, y) in enumerate(zip(got, d["oracle_answers"]["block_sha256"])) if x != y]
+    assert ans.size == d["oracle_answers"]["bytes"] and not bad, \
+        "answers differ from the oracle's in %d of %d blocks of %d bytes (first: %s)" % (
+            len(bad), len(got), ab, bad[:8])
+    assert int(ans.sum(dtype=np.int64)) == d["oracle_answers"]["present"]
+
+
 def sample_records(rng, off, n):
     nrec = off.size - 1
     return np.sort(rng.choice(nrec, size=min(n, nrec), replace=False))
-
-
-def gather_records(seq, off, idx):
-    parts = [seq[int(off[r]):int(off[r + 1])] for r in idx]
-    lens = np.array([p.size for p in parts], dtype=np.uint64)
-    o = np.zeros(len(parts) + 1, dtype=np.uint64)
-    o[1:] = np.cumsum(lens)
-    return np.concatenate(parts), o
-
-
-def check_sampled_answers(p, F, ans, qs, qoff, idx):
-    sq, so = gather_records(qs, qoff, idx)
-    want = oracle.query(p, F, sq, so)
-    got = np.concatenate([ans[int(qoff[r]):int(qoff[r + 1])] for r in idx])
-    assert np.array_equal(got, want), "sampled answers differ at %d positions" % int((got != want).sum())
 
 
 def check_fpr_prediction(p, F, ans, qs, qoff, idx):
@@ -79,6 +112,13 @@ def check_fpr_prediction(p, F, ans, qs, qoff, idx):
     assert abs(got - expect) <= 0.25 * expect + 5 * np.sqrt(expect) + 2
 
 
+def genome_kmers_present(self_ans, off, k):
+    valid = np.ones(self_ans.size, dtype=bool)
+    for r in range(off.size - 1):
+        valid[max(int(off[r]), int(off[r + 1]) - (k - 1)):int(off[r + 1])] = False
+    return bool(self_ans[valid].all()) and not self_ans[~valid].any()
+
+
 def test_in_cache_full_size():
     w = synth.in_cache_workload()
     print("case in-cache full size", flush=True)
@@ -95,43 +135,35 @@ def test_in_cache_full_size():
     ans = d_ans.cpu().numpy()
     self_ans = d_self.cpu().numpy()
     f.close()
-    # every k-mer of the genome is present (no false negatives)
-    valid = np.ones(ins.size, dtype=bool)
-    for r in range(ioff.size - 1):
-        valid[int(ioff[r + 1]) - (w["k"] - 1):int(ioff[r + 1])] = False
-    assert self_ans[valid].all() and not self_ans[~valid].any()
-    # the whole filter equals the oracle's
-    print("oracle insert of 100 Mbp", flush=True)
-    F = oracle.insert(p, p.empty(), ins, ioff)
+    assert genome_kmers_present(self_ans, ioff, w["k"])
+    print("oracle insert of 100 Mbp and query of 2M reads", flush=True)
+    F = oracle.insert_parallel(p, p.empty(), ins, ioff)
     bad = np.flatnonzero(bits != F)
     assert bad.size == 0, "filter differs in %d of %d words" % (bad.size, F.size)
-    # answers of 20k sampled reads, half positive half negative
-    rng = np.random.default_rng(1)
-    idx = sample_records(rng, qoff, 20_000)
-    check_sampled_answers(p, F, ans, qs, qoff, idx)
+    want = oracle.query_parallel(p, F, qs, qoff)
+    bad = np.flatnonzero(ans != want)
+    assert bad.size == 0, "answers differ at %d of %d positions (first %s)" % (bad.size, ans.size, bad[:8])
+    check_against_stored("in_cache", bits, ans)
     # false positives among sampled negative reads match the prediction from
     # the filter's own sector popcounts (ideal s-mer hash); random reads share
     # the genome's 41% GC, which loads shards unevenly, so the uniform-sequence
     # closed form does not apply here
+    rng = np.random.default_rng(1)
     nneg = (qoff.size - 1) // 2
     nidx = nneg + sample_records(rng, qoff[nneg:] - qoff[nneg], 20_000)
     check_fpr_prediction(p, bits, ans, qs, qoff, nidx)
 
 
-@pytest.fixture(scope="module")
-def out_of_cache():
+def test_out_of_cache_full_size():
     w = synth.out_of_cache_workload()
-    return w
-
-
-def test_out_of_cache_full_size(out_of_cache):
-    w = out_of_cache
     print("case out-of-cache full size", flush=True)
     k = w["k"]
     p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
     assert p.nshards == 1 << 28
     ins, ioff = w["insert"]
     qs, qoff = w["query"]
+    d = stored("out_of_cache")
+    assert d["insert"]["bases"] == ins.size and d["query"]["bases"] == qs.size
     f = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
     d_ins = to_dev(ins)
     d_ioff = off_dev(ioff)
@@ -149,25 +181,56 @@ def test_out_of_cache_full_size(out_of_cache):
     assert present == n_valid
     bits = f.get_bits()
     f.close()
-    # sampled answers against the GPU's own filter (query path exactness)
-    rng = np.random.default_rng(2)
+    print("comparing 8 GiB of filter and 3 GB of answers with the oracle's digests", flush=True)
+    check_against_stored("out_of_cache", bits, ans)
     short_n = 10_000_000
-    idx = np.concatenate([sample_records(rng, qoff[: short_n + 1], 6000),
-                          short_n + sample_records(rng, qoff[short_n:] - qoff[short_n], 60)])
-    check_sampled_answers(p, bits, ans, qs, qoff, idx)
-    # a 2 Mbp genome slice inserted alone at full geometry equals the oracle,
-    # and its bits are a subset of the full filter
-    a = int(ioff[3]) + 12_345_678
-    part = ins[a:a + 2_000_000]
-    g = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
-    g.insert(to_dev(part))
-    torch.cuda.synchronize()
-    gbits = g.get_bits()
-    g.close()
-    F = oracle.insert(p, p.empty(), part)
-    assert np.array_equal(gbits, F)
-    assert np.array_equal(bits & F, F)
     fpr = ans[int(qoff[short_n // 2]):int(qoff[short_n])].sum() / (short_n // 2 * (150 - k + 1))
     print("out-of-cache FPR on random reads: %.3g" % fpr, flush=True)
+    rng = np.random.default_rng(2)
     nidx = short_n // 2 + sample_records(rng, qoff[short_n // 2:short_n + 1] - qoff[short_n // 2], 20_000)
     check_fpr_prediction(p, bits, ans, qs, qoff, nidx)
+
+
+def _graph_run(w):
+    from paper_2606_24417_amd import Graph
+
+    ins, ioff = w["insert"]
+    qs, qoff = w["query"]
+    d_ins, d_ioff, d_q, d_qoff = to_dev(ins), off_dev(ioff), to_dev(qs), off_dev(qoff)
+    d_out = torch.full((qs.size,), 7, dtype=torch.uint8, device="cuda")
+    f = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
+    g = Graph(f, d_ins, d_ioff, d_q, d_qoff, d_out, clear_first=True)
+    g.launch()
+    torch.cuda.synchronize()
+    first = d_out.cpu().numpy()
+    d_out.fill_(9)
+    g.launch()  # a replay gives the same filter and answers
+    torch.cuda.synchronize()
+    bits = f.get_bits()
+    ans = d_out.cpu().numpy()
+    g.close()
+    f.close()
+    assert np.array_equal(first, ans)
+    return bits, ans
+
+
+def test_batched_full_size_graph():
+    """The batched workload itself (2M reads of log-normal length up to 50 kbp,
+    inserted and then 2M queried, in one persistent launch each under a HIP
+    graph) against the oracle's stored digests."""
+    w = synth.batched_workload()
+    print("case batched full size", flush=True)
+    d = stored("batched")
+    assert d["insert"]["bases"] == w["insert"][0].size and d["query"]["bases"] == w["query"][0].size
+    bits, ans = _graph_run(w)
+    check_against_stored("batched", bits, ans)
+
+
+def test_batched_reduced_graph_against_oracle():
+    w = synth.batched_workload(0.05)
+    print("case batched 5%", flush=True)
+    p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
+    bits, ans = _graph_run(w)
+    F = oracle.insert_parallel(p, p.empty(), *w["insert"])
+    assert np.array_equal(bits, F)
+    assert np.array_equal(ans, oracle.query_parallel(p, F, *w["query"]))

@@ -341,6 +341,36 @@ def test_union_order_and_record_independence():
     assert np.array_equal(Fk, FA)
 
 
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_parallel_insert_and_query_equal_the_serial_ones(threads):
+    """The threaded forms used on full-size workloads (k-1-overlapping pieces;
+    atomic ORs into one filter) give the serial oracle's filter and answers:
+    OR is commutative and idempotent, and every k-mer start belongs to one
+    piece whose bases contain the whole k-mer."""
+    rng = np.random.default_rng(26 + threads)
+    p = oracle.Params(31, 28, 16, 4, 1 << 14)
+    lengths = [int(x) for x in rng.integers(0, 400, 40)] + [5000, 0, 31, 30]
+    seq = np.frombuffer(rand_dna(rng, sum(lengths), "ACGT" * 30 + "N").encode(), dtype=np.uint8)
+    off = np.concatenate(([0], np.cumsum(lengths))).astype(np.uint64)
+    want = oracle.insert(p, p.empty(), seq, off)
+    got = oracle.insert_parallel(p, p.empty(), seq, off, threads=threads)
+    assert np.array_equal(got, want)
+    assert np.array_equal(oracle.query_parallel(p, want, seq, off, threads=threads), oracle.query(p, want, seq, off))
+    # one long record cut into many pieces
+    one = np.array([0, seq.size], dtype=np.uint64)
+    assert np.array_equal(oracle.insert_parallel(p, p.empty(), seq, one, threads=threads),
+                          oracle.insert(p, p.empty(), seq, one))
+    assert np.array_equal(oracle.query_parallel(p, want, seq, one, threads=threads),
+                          oracle.query(p, want, seq, one, per_base=True))
+    # pieces partition the k-mer starts and cover their k-mers
+    for n in (1, 2, 7, 64):
+        cov = np.zeros(seq.size, dtype=np.int64)
+        for a, b, e, loc in oracle.pieces(off, seq.size, n, 31):
+            cov[a:b] += 1
+            assert e == min(seq.size, b + 30) and loc[0] == 0 and loc[-1] == e - a
+        assert (cov[:seq.size - 30] == 1).all() and not cov[seq.size - 30:].any()
+
+
 def test_query_zero_false_negatives_read_only_and_idempotent():
     rng = np.random.default_rng(23)
     p = oracle.Params(31, 28, 16, 4, 1 << 12)
