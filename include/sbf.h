@@ -153,6 +153,20 @@ int sbf_insert_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const u
 int sbf_query_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
                         uint64_t nrec, uint8_t *d_out, void *stream);
 
+/* Allocation-free form of sbf_query_batch_dev, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * hosts that forbid hipMalloc): same arguments, layout and answers, and it
+ * calls no hipMalloc, hipFree or other allocating routine.  Its scratch (the
+ * record-start bits and the work-queue counters) is one fixed array of 8 MiB
+ * per GPU, held until the process ends, so a batch may have at most 2^26
+ * bases (len > 2^26 returns SBF_E_INVAL).  The array is shared by every call
+ * on that GPU, whatever the filter or stream: calls that overlap on one GPU
+ * (on different streams, or from several host threads) race and must be
+ * ordered by the caller.  The scratch is cleared by fill kernels on `stream`
+ * (no memset), and the filter's launch settings apply.  Stream-ordered. */
+int sbf_query_batch_dev_noalloc(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
+                                uint64_t nrec, uint8_t *d_out, void *stream);
+
 /* The two steps of the device batch form, for callers that reuse one batch
  * or time the kernels apart.  sbf_mark_record_starts_dev zeroes d_starts
  * (ceil(len/32) words) and sets bit off[r] % 32 of word off[r] / 32 for

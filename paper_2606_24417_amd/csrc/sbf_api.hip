@@ -271,6 +271,37 @@ int check_filter(const sbf_filter *f) {
   return SBF_OK;
 }
 
+// Scratch of the allocation-free query (sbf_query_batch_dev_noalloc): the
+// work-queue counters of a persistent launch, then the record-start bits of
+// up to kNoAllocMaxBases bases.  A file-scope device array, one copy per GPU
+// for the life of the process; every call on a GPU shares it.  Host code uses
+// the address hipGetSymbolAddress returns for the current device (kept per
+// device in g_noalloc), never the array's name.
+constexpr uint64_t kNoAllocQueueWords = 64;  // 256 bytes: the counters, at the array's 256-byte alignment
+constexpr uint64_t kNoAllocStartWords = 1ull << 21;
+constexpr uint64_t kNoAllocMaxBases = kNoAllocStartWords * 32;  // 2^26 bases, 8 MiB of scratch
+__device__ __align__(256) uint32_t scratch[kNoAllocQueueWords + kNoAllocStartWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+uint32_t *g_noalloc[kMaxDevices];
+
+// Device address of `scratch` on device dev, which must be current; looked up
+// once per device.
+int noalloc_scratch(int dev, uint32_t **out) {
+  if (dev < 0 || dev >= kMaxDevices) return set_error(SBF_E_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_error(e, "address of the allocation-free scratch");
+    if (p == nullptr) return set_error(SBF_E_DEVICE, "address of the allocation-free scratch is NULL");
+    g_noalloc[dev] = (uint32_t *)p;
+  }
+  *out = g_noalloc[dev];
+  return SBF_OK;
+}
+
 int set_device(const sbf_filter *f) {
   SBF_HIP(hipSetDevice(f->device), "hipSetDevice");
   return SBF_OK;
@@ -583,8 +614,9 @@ sbf_filter *sbf_create_ex(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64
   }
   e = sbf::launch_fill_u64(f->words, nwords, 0ull, f->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
-  if (e != hipSuccess) {
-    hip_error(e, "filter initialisation");
+  uint32_t *noalloc = nullptr;
+  if (e != hipSuccess || noalloc_scratch(f->device, &noalloc) != SBF_OK) {
+    if (e != hipSuccess) hip_error(e, "filter initialisation");
     (void)hipFree(f->words);
     (void)hipStreamDestroy(f->stream);
     delete f;
@@ -704,6 +736,36 @@ int sbf_query_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const ui
   if ((rc = record_starts(f, d_off, nrec, len, st, &starts))) return rc;
   SeqArgs a{(const uint8_t *)d_seq, len, starts, d_out, len};
   if ((rc = run_query(f, a, st))) return rc;
+  return ok();
+}
+
+int sbf_query_batch_dev_noalloc(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
+                                uint64_t nrec, uint8_t *d_out, void *stream) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (len == 0 || nrec == 0) return ok();
+  if (!d_seq || !d_off || !d_out) return set_error(SBF_E_INVAL, "sequence, offsets or output is NULL");
+  if (len > kNoAllocMaxBases)
+    return set_error(SBF_E_INVAL, "batch of %llu bases exceeds the %llu bases of the allocation-free scratch",
+                     (unsigned long long)len, (unsigned long long)kNoAllocMaxBases);
+  if ((rc = set_device(f))) return rc;
+  uint32_t *scr = nullptr;
+  if ((rc = noalloc_scratch(f->device, &scr))) return rc;
+  hipStream_t st = pick(f, stream);
+  const uint32_t *starts = nullptr;
+  if (nrec >= 2) {
+    // the bits of this batch only: clear its words (a fill kernel), then mark
+    uint32_t *w = scr + kNoAllocQueueWords;
+    const uint64_t nw = (len + 31) / 32;
+    hipError_t e = sbf::launch_fill_u32(w, nw, 0u, st);
+    if (e == hipSuccess) e = sbf::launch_mark_record_starts(d_off, nrec, len, w, st);
+    if (e != hipSuccess) return hip_error(e, "record-start marking");
+    starts = w;
+  }
+  // persistent launches take their tile counters from the scratch as well
+  sbf::LaunchShape ls{scr, 0};
+  SeqArgs a{(const uint8_t *)d_seq, len, starts, d_out, len};
+  if ((rc = run_query(f, a, st, &ls))) return rc;
   return ok();
 }
 

@@ -55,6 +55,7 @@ SIGNATURES = {
     "sbf_query_batch": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "sbf_insert_batch_dev": (_int, [_vp, _vp, _u64, _vp, _u64, _vp]),
     "sbf_query_batch_dev": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp]),
+    "sbf_query_batch_dev_noalloc": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp]),
     "sbf_mark_record_starts_dev": (_int, [_vp, _u64, _u64, _vp, _vp]),
     "sbf_insert_marked_dev": (_int, [_vp, _vp, _u64, _vp, _vp]),
     "sbf_query_marked_dev": (_int, [_vp, _vp, _u64, _vp, _vp, _vp]),
@@ -327,6 +328,17 @@ class Filter:
         _check(L.sbf_query_batch(self._h, a.ctypes.data_as(ctypes.c_void_p), off.ctypes.data_as(ctypes.c_void_p),
                                  off.size - 1, res_p))
         return res
+
+
+    def query_batch_dev_noalloc(self, seq, offsets, out, stream=None):
+        """Query a device record batch without any device allocation
+        (sbf_query_batch_dev_noalloc: fixed per-GPU scratch, at most 2^26
+        bases per call, calls on one GPU must not overlap).  ``out`` is a
+        caller-allocated uint8 device tensor of len(seq) bytes."""
+        _check(lib().sbf_query_batch_dev_noalloc(self._h, ctypes.c_void_p(seq.data_ptr()), seq.numel(),
+                                                 ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
+                                                 ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
 
 
 class Graph:
