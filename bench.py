@@ -254,7 +254,7 @@ def stored_segments(workload_name: str, part: str, kmers: int):
     return int(d["segments"])
 
 
-PROBE_NAMES = ["read", "rmw", "atomic4", "atomic1", "copy"]
+PROBE_NAMES = ["read", "rmw", "atomic4", "atomic1", "copy", "read_line", "rmw_line"]
 # in-flight depths compiled into the probe per shard size (include/sbf_probe.h)
 PROBE_DEPTHS = {32: (1, 4, 8, 16), 64: (1, 4, 8), 128: (1, 2, 4)}
 PROBE_WGS = (1, 2, 4, 8)
@@ -741,13 +741,75 @@ def bench_sweep(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_fpr_curve(args):
+    """False-positive rate against filter size (Section "False Positive Rate":
+    independent random k-mers queried after a genome insert): the in-cache
+    genome (scaled by --scale) is inserted at (31, 28, 16, 4) into filters of
+    2^22 .. 2^38 and 2^39 bits, with 4- and 16-word shards, and --fpr-kmers
+    independent uniform random 31-mers (generated on the device in batches of
+    2^26, each k-mer followed by an 'N' so that it is its own record, and kept
+    resident) are queried.  Each point reports the measured count of k-mers
+    answered present beside the filter's own prediction (sbf_estimate_fpr: the
+    mean over shards of the product of its sectors' set-bit fractions, the
+    exact expectation for uniformly sharded queries with ideal s-mer hashes)
+    and the 99.9% Poisson interval of that expectation."""
+    import torch
+    from scipy.stats import poisson
+
+    from paper_2606_24417_amd import Filter
+
+    t0 = time.perf_counter()
+    w = synth.in_cache_workload(args.scale)
+    k = w["k"]
+    ins, ioff = w["insert"]
+    n_ins = kmer_positions(ioff, k)
+    dev = torch.device("cuda:0")
+    d_ins = torch.from_numpy(ins).to(dev)
+    d_ioff = torch.from_numpy(ioff.view(np.int64)).to(dev)
+    total = int(args.fpr_kmers)
+    per = 1 << 26
+    batches = []
+    for i in range((total + per - 1) // per):
+        n = min(per, total - i * per)
+        batches.append(synth.separated_uniform_kmers(n, k, 7000 + i, device=dev))
+    out = torch.empty(per * (k + 1), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    print("[bench] fpr curve: %d genome k-mers, %d random %d-mers in %d batches ready in %.1fs" % (
+        n_ins, total, k, len(batches), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    sizes = [1 << lg for lg in range(22, 39, 2)] + [1 << 39]
+    rows = []
+    for S in (4, 16):
+        for bits in sizes:
+            f = Filter(k, 28, 16, 4, bits, shard_words=S)
+            f.insert(d_ins, d_ioff)
+            est, set_bits = f.estimate_fpr()
+            present = 0
+            for b in batches:
+                o = f.query(b, out=out[: b.numel() - k + 1])
+                present += int(o.sum(dtype=torch.int64).item())
+            f.close()
+            mu = total * est
+            lo, hi = (int(poisson.ppf(0.0005, mu)), int(poisson.ppf(0.9995, mu))) if mu > 0 else (0, 0)
+            rows.append({"shard_words": S, "bits": bits, "bits_per_kmer": round(bits / n_ins, 3),
+                         "set_fraction": round(set_bits / bits, 6), "present": present, "fpr": present / total,
+                         "predicted_fpr": est, "expected": round(mu, 3), "interval_99_9": [lo, hi],
+                         "within": bool(lo <= present <= hi)})
+            print("[bench] S=%2d bits 2^%d: %d present (%.3g), predicted %.4g [%d, %d]" % (
+                S, bits.bit_length() - 1, present, present / total, mu, lo, hi), file=sys.stderr, flush=True)
+    res = {"metric": "FPR of independent uniform random 31-mers vs filter size at (31,28,16,4)", "unit": "fpr",
+           "random_kmers": total, "rows": rows, "all_within_interval": all(r["within"] for r in rows),
+           "config": {"workload": w["name"] + " (scale %g)" % args.scale, "genome_kmers": n_ins}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="out_of_cache",
-                    choices=["in_cache", "out_of_cache", "tiny", "batched", "served", "host", "sweep"])
+                    choices=["in_cache", "out_of_cache", "tiny", "batched", "served", "host", "sweep", "fpr_curve"])
+    ap.add_argument("--fpr-kmers", type=float, default=1e9, help="fpr_curve: random k-mers per filter size")
     ap.add_argument("--sweep-points", type=int, default=0, help="sweep: only the first n (s,m,H) points")
     ap.add_argument("--staging-mib", type=int, default=0, help="host: chunk size of the host entry points")
     ap.add_argument("--scale", type=float, default=1.0, help="batched/served workload size factor")
@@ -760,7 +822,10 @@ def main():
                     help="out_of_cache: skip the in-cache workload reported as a second key")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the live roofline probes (random access out of cache, 32-bit add rate in cache)")
-    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic")
+    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic, 3 wide-shard")
+    ap.add_argument("--shard-words", type=int, default=4, choices=[4, 8, 16],
+                    help="64-bit words per shard (4 = the paper's 256-bit shard)")
+    ap.add_argument("--tile", type=str, default="", help="k-mers per lane for insert,query (0 = default)")
     ap.add_argument("--bits", type=int, default=0, help="filter size override (default: the workload's)")
     ap.add_argument("--query-mode", type=int, default=0, help="0 lane-sequential, 1 leader load + broadcast, 2 every lane loads")
     ap.add_argument("--insert-mode", type=int, default=0, help="0 two-pass, 1 atomic")
@@ -784,6 +849,7 @@ def main():
     if args.probe:
         run_probes([2, 32, 256, 1024, 8192])
         run_probes([8192], modes=(0, 1), shard_bytes=(64, 128))
+        run_probes([8192], modes=(5, 6), shard_bytes=(32, 64, 128))
         for mib in (2, 32, 256, 8192):
             run_copy_probe(mib)
         run_valu_probes()
@@ -812,6 +878,9 @@ def main():
         return
     if args.workload == "sweep":
         bench_sweep(args)
+        return
+    if args.workload == "fpr_curve":
+        bench_fpr_curve(args)
         return
 
     res = measure(args, args.workload, with_cpu=not args.no_cpu_baseline)
@@ -849,6 +918,9 @@ def measure(args, name, with_cpu):
     w = workload(name)
     if args.bits:
         w["bits"] = args.bits
+    S = args.shard_words
+    # stored oracle results (segment counts, digests) of this workload at this geometry
+    key = name if S == 4 else "%s_S%d" % (name, S)
     t_gen = time.perf_counter() - t_gen
     k = w["k"]
     ins, ioff = w["insert"]
@@ -864,9 +936,11 @@ def measure(args, name, with_cpu):
     d_q = torch.from_numpy(qs).to(dev)
     d_qoff = torch.from_numpy(qoff.view(np.int64)).to(dev)
     d_out = torch.empty(qs.size, dtype=torch.uint8, device=dev)
-    f = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"])
+    f = Filter(w["k"], w["s"], w["m"], w["H"], w["bits"], shard_words=S)
     if args.variant:
         f.variant = args.variant
+    if args.tile:
+        f.set_tile(*(int(x) for x in args.tile.split(",")))
     f.set_query_mode(args.query_mode)
     f.set_insert_mode(args.insert_mode)
     if args.launch:
@@ -914,7 +988,7 @@ def measure(args, name, with_cpu):
     # whole workload, stored by tests/golden/segment_counts.py.
     ans = d_out.cpu().numpy()
     n_q_valid = int(ans.sum(dtype=np.int64))
-    stored = stored_oracle(name)
+    stored = stored_oracle(key)
     check = {"ok": None, "note": "no stored oracle result for this workload"}
     if stored and "oracle_answers" in stored and stored["query"]["bases"] == qs.size and not args.bits:
         ans_ok = _sha256(ans) == stored["oracle_answers"]["sha256"]
@@ -932,9 +1006,20 @@ def measure(args, name, with_cpu):
     # Roofline of the dominant work: the insert is two launches (store pass,
     # then repair walk) unless it runs in atomic mode; the query is one.
     settings = f.get_launch()
+    family = {1: "lane", 2: "generic", 3: "wide-shard"}[f.variant]
+    tile_i, tile_q = f.get_tile()
+    settings.update({"family": family, "shard_words": S, "insert_kmers_per_lane": tile_i,
+                     "query_kmers_per_lane": tile_q})
     ins_launches = 1 if settings["insert_mode"] == 1 else 2
-    q_kernel = {0: "query_lane_kernel", 1: "query_rolling_kernel (leader)", 2: "query_rolling_kernel (direct)"}[
-        settings["query_mode"]] + "<31,28,16,4>"
+    if family == "wide-shard":
+        q_kernel = "query_wide_kernel<31,28,16,4,%d,%d>" % (S, tile_q)
+        ins_kernels = ("insert_wide_kernel<31,28,16,4,%d,%d> store pass + query_wide_kernel<31,28,16,4,%d,%d> repair "
+                       "walk" % (S, tile_i, S, tile_i), "insert_wide_kernel<31,28,16,4,%d,%d> (atomic)" % (S, tile_i))
+    else:
+        q_kernel = {0: "query_lane_kernel", 1: "query_rolling_kernel (leader)", 2: "query_rolling_kernel (direct)"}[
+            settings["query_mode"]] + "<31,28,16,4>"
+        ins_kernels = ("insert_rolling_kernel<31,28,16,4> store pass + query_lane_kernel<31,28,16,4> repair walk",
+                       "insert_rolling_kernel<31,28,16,4> (atomic)")
     in_cache = name != "out_of_cache"
 
     valu = None
@@ -942,13 +1027,18 @@ def measure(args, name, with_cpu):
         valu = round(valu_rate(SBF_PROBE_VALU_ADD32) * 64 / 1e12, 2)
     probe = None
     if not in_cache and not args.no_probe:
-        # ceilings of random 32-byte shard reads and read-modify-writes over an
-        # 8 GiB buffer (best over in-flight depth and occupancy), measured now
+        # ceilings of random shard reads and read-modify-writes of this shard
+        # size over an 8 GiB buffer (best over in-flight depth and occupancy,
+        # with the shard moved by one lane or split over shard/16 lanes as the
+        # wide-shard kernels do), measured now
         probe = {}
-        for mode in (0, 1):
-            best, table = probe_ceiling(8192, mode, 32)
-            probe[PROBE_NAMES[mode]] = best
-        print("[bench] random-access ceilings (8 GiB, 32 B): %s" % json.dumps(probe), file=sys.stderr, flush=True)
+        sb = 8 * S
+        for mode, line_mode in ((0, 5), (1, 6)):
+            best, _ = probe_ceiling(8192, mode, sb)
+            best_l, _ = probe_ceiling(8192, line_mode, sb)
+            best_l["lanes_per_shard"] = sb // 16
+            probe[PROBE_NAMES[mode]] = best if best["G_per_s"] >= best_l["G_per_s"] else best_l
+        print("[bench] random-access ceilings (8 GiB, %d B): %s" % (sb, json.dumps(probe)), file=sys.stderr, flush=True)
 
     def roofline(part, ms, kmers, launches):
         if in_cache:
@@ -957,13 +1047,13 @@ def measure(args, name, with_cpu):
             r = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT_TOPS, "unit": "TOP/s (int32)",
                  "frac": round(achieved / PEAK_INT_TOPS, 4), "ops_per_kmer": OPS_PER_KMER[part]}
         else:
-            nseg = stored_segments(name, part, kmers)
+            nseg = stored_segments(key, part, kmers)
             seqs = w[part]
             if nseg is None:
                 r = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
                      "note": "no stored segment count for this workload"}
             else:
-                per_seg = 32 if part == "query" else 64
+                per_seg = 8 * S if part == "query" else 16 * S
                 nbytes = nseg * per_seg + seqs[0].size * (2 if part == "query" else 1)
                 achieved = nbytes / (ms * 1e-3) / 1e9
                 r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -984,7 +1074,7 @@ def measure(args, name, with_cpu):
             best = probe["read" if part == "query" else "rmw"]
             peak = best["G_per_s"] * 1e9
             r["random_access"] = {"segments_per_s": seg_rate, "probe_ceiling_per_s": peak,
-                                  "probe": ("read" if part == "query" else "read-modify-write") + " 32 B",
+                                  "probe": ("read" if part == "query" else "read-modify-write") + " %d B" % (8 * S),
                                   "probe_setting": {"inflight": best["inflight"], "wgs_per_cu": best["wgs_per_cu"]},
                                   "frac": round(seg_rate / peak, 4)}
         r["launches"] = launches
@@ -996,8 +1086,7 @@ def measure(args, name, with_cpu):
     roof_q = roofline("query", q_mean, n_q_kmers, 1)
     roof_q["kernel"] = q_kernel
     roof_i = roofline("insert", i_mean, n_ins_kmers, ins_launches)
-    roof_i["kernel"] = ("insert_rolling_kernel<31,28,16,4> store pass + query_lane_kernel<31,28,16,4> repair walk"
-                        if ins_launches == 2 else "insert_rolling_kernel<31,28,16,4> (atomic)")
+    roof_i["kernel"] = ins_kernels[0] if ins_launches == 2 else ins_kernels[1]
     if q_mean >= i_mean / ins_launches:
         roof, roof_other = roof_q, roof_i
     else:
@@ -1017,7 +1106,7 @@ def measure(args, name, with_cpu):
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": w["name"], "k": w["k"], "s": w["s"], "m": w["m"], "H": w["H"],
-                   "filter_bits": f.num_bits, "insert_kmers": n_ins_kmers, "query_kmers": n_q_kmers,
+                   "filter_bits": f.num_bits, "shard_words": S, "insert_kmers": n_ins_kmers, "query_kmers": n_q_kmers,
                    "insert_valid_kmers": valid_kmers(ins, ioff, k), "query_valid_kmers": valid_kmers(qs, qoff, k),
                    "parallelism": "single GPU"},
         "p50_batch_ms": round(float(np.percentile(step_ms, 50)), 4),

@@ -50,9 +50,10 @@ extern "C" {
 #define SBF_E_BUSY (-4)   /* a request was not admitted: the server's queue is full */
 
 /* Kernel families (sbf_set_variant). */
-#define SBF_VARIANT_AUTO 0    /* rolling kernel when compiled for (k,s,m,H), else generic */
-#define SBF_VARIANT_ROLLING 1 /* super-k-mer rolling kernels (specialised parameter sets) */
+#define SBF_VARIANT_AUTO 0    /* super-k-mer kernels when compiled for (k,s,m,H) and the shard size, else generic */
+#define SBF_VARIANT_ROLLING 1 /* super-k-mer kernels: lane kernels for 4-word shards, wide-shard kernels for 8/16 */
 #define SBF_VARIANT_GENERIC 2 /* one k-mer per lane, run-time k, s, m, H */
+#define SBF_VARIANT_WIDE 3    /* wide-shard (two-phase, whole-line) super-k-mer kernels, also for 4-word shards */
 
 typedef struct sbf_filter sbf_filter; /* opaque; owns its device bit array */
 
@@ -76,9 +77,10 @@ sbf_filter *sbf_create(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t 
  * the s-mer hash just above the t-th 6-bit bit address, which needs
  * 64/H >= 6 + log2(S/4) (H <= 9 for S = 8, H <= 8 for S = 16).  The shard
  * count is the power of two at or above ceil(bits / (64 S)).  Filters with
- * S = 8 or 16 run the generic kernels; bits and answers differ from S = 4,
- * so S is part of the filter's definition, not a tuning setting.  Errors as
- * sbf_create. */
+ * S = 8 or 16 run the wide-shard super-k-mer kernels where they are compiled
+ * for (k, s, m, H), else the generic kernels; bits and answers differ from
+ * S = 4, so S is part of the filter's definition, chosen at creation
+ * (sbf_autotune_geometry measures it).  Errors as sbf_create. */
 sbf_filter *sbf_create_ex(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits, uint32_t shard_words);
 
 /* Free the filter and its device memory after waiting for its stream.
@@ -119,6 +121,17 @@ int sbf_set_bits(sbf_filter *f, const uint64_t *host_src, uint64_t nwords);
  * not synchronise. */
 int sbf_clear(sbf_filter *f, void *stream);
 
+/* Load statistics (Section "False Positive Rate"; Eq. 1 per sector and Eq. 2
+ * across the k-s+1 s-mers): *fpr receives the false-positive rate expected
+ * for k-mers absent from the filter whose shard is uniform over the shards
+ * and whose s-mers hash independently and ideally, i.e. the mean over shards
+ * of the product over sectors c of p_c^((k-s+1) n_c), with p_c the fraction of
+ * set bits in the shard's words of sector c and n_c the hash indices t < H
+ * with t mod 4 = c; *set_bits receives the number of set bits.  Either
+ * pointer may be NULL (not both).  Waits for all work on the device first;
+ * synchronous.  It reads the bit array only. */
+int sbf_estimate_fpr(const sbf_filter *f, double *fpr, uint64_t *set_bits);
+
 /* Device pointer of the bit array (S * N words).  Valid until sbf_destroy. */
 const uint64_t *sbf_device_words(const sbf_filter *f);
 
@@ -145,8 +158,8 @@ int sbf_query_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_
  * be 0 and off[nrec] must equal len).  Stream-ordered.  The library keeps one
  * scratch buffer of len/8 bytes per stream used (record starts as bits).
  * Queries on different streams may overlap one another; inserts into one
- * filter must not overlap another insert under SBF_INSERT_TWO_PASS (a plain
- * store of one could undo a bit the other has already repaired): order them
+ * filter must not overlap another insert under SBF_INSERT_TWO_PASS (a store
+ * of one could undo a bit the other has already repaired): order them
  * on one stream or with events, or use SBF_INSERT_ATOMIC. */
 int sbf_insert_batch_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint64_t *d_off,
                          uint64_t nrec, void *stream);
@@ -180,16 +193,36 @@ int sbf_insert_marked_dev(sbf_filter *f, const char *d_seq, uint64_t len, const 
 int sbf_query_marked_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint32_t *d_starts,
                          uint8_t *d_out, void *stream);
 
-/* Choose the kernel family (SBF_VARIANT_*).  SBF_VARIANT_ROLLING fails with
- * SBF_E_INVAL when no rolling kernel is compiled for the filter's (k,s,m,H).
- * Both families give bit-identical filters and answers. */
+/* Choose the kernel family (SBF_VARIANT_*).  SBF_VARIANT_ROLLING and
+ * SBF_VARIANT_WIDE fail with SBF_E_INVAL when no such kernel is compiled for
+ * the filter's (k,s,m,H) and shard size.  Every family gives bit-identical
+ * filters and answers.  Changing the family resets the tile lengths
+ * (sbf_set_tile) to the new family's defaults. */
 int sbf_set_variant(sbf_filter *f, int variant);
-int sbf_get_variant(const sbf_filter *f); /* the family in effect (1 or 2) */
+/* The family in effect: SBF_VARIANT_ROLLING (4-word lane kernels),
+ * SBF_VARIANT_WIDE or SBF_VARIANT_GENERIC. */
+int sbf_get_variant(const sbf_filter *f);
+
+/* Tile size of the super-k-mer kernels, as k-mers per lane (a tile is 256
+ * lanes of them; with about 8.5 k-mers per super-k-mer, Section "Minimizers
+ * and Super-k-mers", that is the tile's super-k-mer count times 8.5 / 256).
+ * 0 selects the family's default.  Compiled lengths:
+ *   4-word lane kernels, (31,28,16,4) only: insert 32 (default) or 64 k-mers
+ *     per lane for the store pass; query 48 (default) or 32, which the
+ *     insert's repair walk uses as well;
+ *   wide-shard kernels: 16 (default) or 32 for insert and query.
+ * Other values (and any value for the generic kernels) return SBF_E_INVAL.
+ * The result does not depend on the tile size.  sbf_get_tile reads the
+ * effective lengths back (0 for the generic kernels; pointers may be NULL). */
+int sbf_set_tile(sbf_filter *f, uint32_t insert_kmers_per_lane, uint32_t query_kmers_per_lane);
+int sbf_get_tile(const sbf_filter *f, uint32_t *insert_kmers_per_lane, uint32_t *query_kmers_per_lane);
 
 /* How the rolling insert kernel writes finished super-k-mer segments:
- *   SBF_INSERT_TWO_PASS (default): a pass of plain read-OR-write updates of
- *     each segment's shard, then a second pass over the same segments that
- *     atomically ORs back any bit a concurrent update overwrote;
+ *   SBF_INSERT_TWO_PASS (default): a pass of read-OR-write updates of each
+ *     segment's shard (stores that write through to the device's coherence
+ *     point, so that racing updates only drop each other's bits), then a
+ *     second pass over the same segments that atomically ORs back any bit a
+ *     concurrent update overwrote;
  *   SBF_INSERT_ATOMIC: one 64-bit atomic OR per shard word, as in the paper's
  *     Algorithm 1.
  * Both produce the same filter; the generic kernel always uses atomics. */
@@ -242,17 +275,38 @@ int sbf_graph_launch(sbf_graph *g, void *stream);
 void sbf_graph_destroy(sbf_graph *g);
 
 /* Autotuner: on the given device insert and query batches, time every insert
- * strategy and query organisation with one workgroup per tile and with
- * persistent grids of 1, 2, 4 and 8 workgroups per CU (median of three runs
- * after a warm-up) on f itself, whose words are first saved to a temporary
- * device buffer of the filter's size and restored afterwards (f's contents
- * are unchanged; the buffer must fit in device memory), then apply the
- * fastest settings to f.  A text report of
+ * strategy, query organisation and compiled tile length (sbf_set_tile) with
+ * one workgroup per tile and with persistent grids of 1, 2, 4 and 8
+ * workgroups per CU (median of three runs after a warm-up) on f itself, whose
+ * words are first saved to a temporary device buffer of the filter's size
+ * and restored afterwards (f's contents are unchanged; the buffer must fit in
+ * device memory), then apply the fastest settings to f.  A text report of
  * every timing is written to report (NUL-terminated, truncated to
  * report_len; may be NULL).  Synchronous. */
 int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec,
                  const char *d_q, uint64_t q_len, const uint64_t *d_q_off, uint64_t q_nrec, char *report,
                  uint64_t report_len);
+
+/* Shard-geometry autotuner (Section "Data Layout": the shard is sized to the
+ * memory system).  For shards of 4, 8 and 16 words (those valid for H), it
+ * creates a filter of the given parameters and size on the current device,
+ * runs sbf_autotune on it with the insert and query device batches (record
+ * batches as in sbf_insert_batch_dev), then inserts the insert batch and
+ * measures the false-positive rate on the negative batch (k-mers answered
+ * present over its valid k-mers; every valid k-mer of a full filter answers
+ * present, which counts them).  It returns the geometry with the lowest
+ * insert + query time among those whose FPR is at most max_fpr, or, if none
+ * is, the one with the lowest FPR, in *shard_words (required) with its tuned
+ * tile lengths and its FPR (optional outputs, may be NULL).  The shard size
+ * changes the filter's bits, so the caller creates its filter with it
+ * (sbf_create_ex).  A report of every trial is written to report as in
+ * sbf_autotune.  Synchronous; each trial filter is freed before the next. */
+int sbf_autotune_geometry(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits, const char *d_ins,
+                          uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec, const char *d_q,
+                          uint64_t q_len, const uint64_t *d_q_off, uint64_t q_nrec, const char *d_neg,
+                          uint64_t neg_len, const uint64_t *d_neg_off, uint64_t neg_nrec, double max_fpr,
+                          uint32_t *shard_words, uint32_t *insert_kmers_per_lane, uint32_t *query_kmers_per_lane,
+                          double *fpr, char *report, uint64_t report_len);
 
 /* Served form: a request loop over a resident filter with continuous
  * batching.  The server runs a scheduler thread with `slots` execution slots

@@ -205,6 +205,85 @@ __global__ void mark_starts_kernel(const uint64_t *__restrict__ off, uint64_t nr
   }
 }
 
+// Add the number of nonzero bytes of p[0, n) to *count: 16 bytes per lane
+// per step where aligned, a wave reduction, one atomic per wave.
+__global__ void count_nonzero_u8_kernel(const uint8_t *__restrict__ p, uint64_t n, unsigned long long *count) {
+  uint64_t c = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t head = ((16u - ((uintptr_t)p & 15u)) & 15u) < n ? ((16u - ((uintptr_t)p & 15u)) & 15u) : n;
+  const uint64_t nvec = (n - head) / 16;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid < head) c += p[tid] != 0;
+  const uint4 *v = reinterpret_cast<const uint4 *>(p + head);
+  for (uint64_t i = tid; i < nvec; i += stride) {
+    const uint4 x = v[i];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t y = w == 0 ? x.x : w == 1 ? x.y : w == 2 ? x.z : x.w;
+      // a byte is nonzero when any of its bits is set
+      const uint32_t z = (((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y) & 0x80808080u;
+      c += (uint64_t)__popc(z);
+    }
+  }
+  for (uint64_t i = head + nvec * 16 + tid; i < n; i += stride) c += p[i] != 0;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+
+// x^e for a small non-negative integer e (square and multiply).
+__device__ __forceinline__ double ipow(double x, int e) {
+  double r = 1.0;
+  while (e) {
+    if (e & 1) r *= x;
+    x *= x;
+    e >>= 1;
+  }
+  return r;
+}
+
+// Load statistics of a filter: *sum += over shards of the probability that a
+// k-mer sent to that shard with k-s+1 s-mers of independent ideal hashes finds
+// all its bits set, i.e. the product over sectors c of p_c^((k-s+1) n_c), where
+// p_c is the fraction of set bits among the sector's words (the word of a hash
+// index is uniform among its sector's S/4 words) and n_c the number of hash
+// indices t < H with t mod 4 = c (Eq. 1 per sector, Eq. 2 across s-mers);
+// *bits += the set bits.  One shard per lane, a wave reduction, one atomic
+// per wave.
+template <int SW>
+__global__ void estimate_fpr_kernel(const uint64_t *__restrict__ words, uint64_t nshards, int H, int z1, double *sum,
+                                    unsigned long long *bits) {
+  constexpr int G = SW / 4;
+  int expo[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) expo[c] = z1 * ((H - c + 3) / 4);  // hash indices t < H with t mod 4 = c
+  double acc = 0.0;
+  uint64_t ones = 0;
+  for (uint64_t sh = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; sh < nshards;
+       sh += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t *w = words + sh * SW;
+    double prob = 1.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      int pop = 0;
+#pragma unroll
+      for (int g = 0; g < G; ++g) pop += __popcll(w[c + 4 * g]);
+      ones += (uint64_t)pop;
+      prob *= ipow((double)pop / (64.0 * G), expo[c]);
+    }
+    acc += prob;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    acc += __shfl_xor(acc, d, 64);
+    ones += __shfl_xor(ones, d, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (acc != 0.0) atomicAdd(sum, acc);
+    if (ones) atomicAdd(bits, (unsigned long long)ones);
+  }
+}
+
 unsigned grid_for(uint64_t n, unsigned block) {
   uint64_t g = (n + block - 1) / block;
   if (g > 65536u) g = 65536u;
@@ -242,6 +321,36 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_nonzero_u8(const uint8_t *p, uint64_t n, uint64_t *count, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(count_nonzero_u8_kernel, dim3(grid_for((n + 15) / 16, 256)), dim3(256), 0, st, p, n,
+                     (unsigned long long *)count);
+  return hipGetLastError();
+}
+
+hipError_t launch_estimate_fpr(const Geometry &g, const uint64_t *words, double *sum, uint64_t *bits,
+                               hipStream_t st) {
+  const unsigned grid = grid_for(g.nshards, 256);
+  const int z1 = (int)(g.k - g.s + 1);
+  switch (g.shard_words) {
+    case 4:
+      hipLaunchKernelGGL(estimate_fpr_kernel<4>, dim3(grid), dim3(256), 0, st, words, g.nshards, (int)g.H, z1, sum,
+                         (unsigned long long *)bits);
+      break;
+    case 8:
+      hipLaunchKernelGGL(estimate_fpr_kernel<8>, dim3(grid), dim3(256), 0, st, words, g.nshards, (int)g.H, z1, sum,
+                         (unsigned long long *)bits);
+      break;
+    case 16:
+      hipLaunchKernelGGL(estimate_fpr_kernel<16>, dim3(grid), dim3(256), 0, st, words, g.nshards, (int)g.H, z1, sum,
+                         (unsigned long long *)bits);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

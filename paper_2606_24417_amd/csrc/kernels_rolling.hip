@@ -11,9 +11,9 @@
 //     shard changes); the lane ORs the one-hot masks of the segment's s-mers
 //     in registers and writes the segment's shard once when it ends - the
 //     per-lane form of the paper's segmented reduction (Algorithm 1) - either
-//     as four 64-bit atomic ORs or, by default, as a plain read-OR-write
-//     followed by a second pass that atomically restores any bit a racing
-//     write dropped;
+//     as four 64-bit atomic ORs or, by default, as a read-OR-write (plain
+//     load, device-coherent store) followed by a second pass that atomically
+//     restores any bit a racing write dropped;
 //   * the default query (query_lane_kernel) walks k-mers the same way, builds
 //     each k-mer's mask of (k-s+1)*H bits and tests it against the k-mer's
 //     shard, which a lane loads once per run of equal shards (the paper's
@@ -25,87 +25,12 @@
 // commutative and idempotent, and a k-mer is tested in its own shard.
 #include "sbf_device.h"
 #include "sbf_internal.h"
+#include "sbf_tiles.h"
 
 #include <type_traits>
 
 namespace sbf {
 namespace {
-
-// Granules (16 bases) a lane reads: L + K - 1 bases plus one for the funnel
-// shift of the last window.
-template <int K, int L>
-constexpr int lane_granules() { return (L + K - 1 + 15) / 16 + 1; }
-
-// Bit r: k-mer r of a lane is valid (all its bases are A/C/G/T and no record
-// starts inside it).  The lane's bases start at granule g0 of the staged
-// tile; k-mers 0..31 are judged on the 64 bases from granule g0 on, k-mers
-// 32..L-1 on the 64 bases from granule g0 + 2 on.
-template <int K, int L>
-__device__ __forceinline__ uint64_t lane_kmer_valid(const uint32_t *s_vb, int g0) {
-  static_assert(L % 16 == 0 && L <= 64 && (L <= 32 ? L + K - 1 <= 64 : L + K - 1 <= 96),
-                "k-mer validity comes from one or two 64-base windows");
-  auto window = [&](int g) {
-    uint64_t vbits = 0, sbits = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t vb = s_vb[g0 + g + i];
-      vbits |= (uint64_t)(vb & 0xFFFFu) << (16 * i);
-      sbits |= (uint64_t)(vb >> 16) << (16 * i);
-    }
-    return kmer_valid_mask<K>(vbits, sbits);
-  };
-  if constexpr (L <= 32) {
-    return window(0) & ((1ull << L) - 1);
-  } else {
-    return (window(0) & 0xFFFFFFFFull) | ((window(2) & ((1ull << (L - 32)) - 1)) << 32);
-  }
-}
-
-// Tile scheduler.  A plain launch runs tile blockIdx.x once; a persistent
-// launch (counter not null) keeps taking the next tile index from a device
-// counter (the work queue) until all ntiles are taken.  The decision is
-// uniform over the workgroup, so every wave leaves the loop together.
-struct TileQueue {
-  uint32_t *counter;
-  uint32_t ntiles;
-};
-
-__device__ __forceinline__ bool next_tile(const TileQueue &q, uint32_t *s_slot, bool first, uint64_t &tile) {
-  if (q.counter == nullptr) {
-    tile = blockIdx.x;
-    return first;
-  }
-  __syncthreads();  // every lane has read the previous slot
-  if (threadIdx.x == 0) *s_slot = atomicAdd(q.counter, 1u);
-  __syncthreads();
-  tile = *s_slot;
-  return tile < q.ntiles;
-}
-
-// Minimizer hash h_M of the m-mer at window position j (2m-bit value, first
-// base most significant; m <= 16 fits 32 bits).
-template <int M>
-__device__ __forceinline__ uint64_t mmer_hash(const uint32_t *a, int j) {
-  static_assert(M >= 1 && M <= 32, "m-mers fit 64 bits");
-  if constexpr (M <= 16) {
-    return minimizer_hash32(win32(a, j) >> (32 - 2 * M));
-  } else {
-    const uint32_t hi = win32(a, j) >> (64 - 2 * M);
-    const uint32_t lo = win32(a, j + M - 16);
-    return minimizer_hash(((uint64_t)hi << 32) | lo);
-  }
-}
-
-template <int S>
-__device__ __forceinline__ uint64_t smer_at(const uint32_t *a, int j) {
-  if constexpr (S <= 16) {
-    return (uint64_t)(win32(a, j) >> (32 - 2 * S));
-  } else {
-    const uint32_t hi = win32(a, j) >> (64 - 2 * S);
-    const uint32_t lo = win32(a, j + S - 16);
-    return ((uint64_t)hi << 32) | lo;
-  }
-}
 
 template <int H>
 __device__ __forceinline__ void smer_onehots(uint64_t g, uint64_t (&oh)[4]) {
@@ -118,9 +43,11 @@ __device__ __forceinline__ void smer_onehots(uint64_t g, uint64_t (&oh)[4]) {
 // at a fixed ~27 G ops/s whatever the filter size, while plain random 32-byte
 // read-modify-writes run several times faster, so the default insert is two
 // passes over the same k-mers:
-//   kStore:  read the shard, OR the segment's masks, write it back (plain
-//            accesses; a read-modify-write racing with another one on the
-//            same shard can lose that one's bits, never older bits);
+//   kStore:  read the shard, OR the segment's masks, write it back (a plain
+//            load and a store that writes through to the device's coherence
+//            point, store_pair_coherent; a read-modify-write racing with
+//            another one on the same shard can lose that one's bits, never
+//            older bits);
 //   repair:  the lane query walk (query_lane_kernel with REPAIR) tests every
 //            valid k-mer against its shard and atomically ORs the bits still
 //            missing (a few percent of the segments in cache, fewer out of
@@ -205,12 +132,10 @@ __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uin
 #pragma unroll
     for (int k = 0; k < kQueueSlots; ++k) {
       if (k < n) {
-        uint64_t v[4];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) v[w] = old[k][w] | m[k][w];
-        uint4 *p = reinterpret_cast<uint4 *>(words + 4ull * (uint64_t)sh[k]);
-        p[0] = make_uint4((uint32_t)v[0], (uint32_t)(v[0] >> 32), (uint32_t)v[1], (uint32_t)(v[1] >> 32));
-        p[1] = make_uint4((uint32_t)v[2], (uint32_t)(v[2] >> 32), (uint32_t)v[3], (uint32_t)(v[3] >> 32));
+        // coherent stores: see store_pair_coherent
+        uint64_t *p = words + 4ull * (uint64_t)sh[k];
+        store_pair_coherent(p, old[k][0] | m[k][0], old[k][1] | m[k][1]);
+        store_pair_coherent(p + 2, old[k][2] | m[k][2], old[k][3] | m[k][3]);
       }
     }
     n = 0;
@@ -667,12 +592,18 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
             const bool fresh = r == 0 || sh != prev_sh;
             prev_sh = sh;
             const uint32_t lsh = fresh ? sh : 0u;
-            const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)lsh);
-            const uint4 lo = p[0], hi = p[1];
-            ldw[r][0] = ((uint64_t)lo.y << 32) | lo.x;
-            ldw[r][1] = ((uint64_t)lo.w << 32) | lo.z;
-            ldw[r][2] = ((uint64_t)hi.y << 32) | hi.x;
-            ldw[r][3] = ((uint64_t)hi.w << 32) | hi.z;
+            if constexpr (REPAIR) {
+              // the repair's reads race with its own atomic ORs: atomic loads
+#pragma unroll
+              for (int w = 0; w < 4; ++w) ldw[r][w] = load_word(words + 4ull * (uint64_t)lsh + w);
+            } else {
+              const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)lsh);
+              const uint4 lo = p[0], hi = p[1];
+              ldw[r][0] = ((uint64_t)lo.y << 32) | lo.x;
+              ldw[r][1] = ((uint64_t)lo.w << 32) | lo.z;
+              ldw[r][2] = ((uint64_t)hi.y << 32) | hi.x;
+              ldw[r][3] = ((uint64_t)hi.w << 32) | hi.z;
+            }
             fresh_at[r] = fresh;
             sh_at[r] = sh;
             smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);
@@ -758,55 +689,67 @@ constexpr int kQueryLaneL = 48;
 constexpr int kQueryLaneWG = 256;
 constexpr int kQueryLaneD = 1;
 
-// Grid of a launch over ntiles tiles: one workgroup per tile, or a persistent
-// grid that takes tiles from the queue counter `slot` (reset first).  A batch
-// of no more tiles than the persistent grid has workgroups runs as a plain
-// launch: the same tiles, one per workgroup, without the counter reset.
-hipError_t tile_grid(uint64_t ntiles, const LaunchShape &ls, int slot, hipStream_t st, TileQueue &tq,
-                     unsigned &grid) {
-  tq.counter = nullptr;
-  tq.ntiles = (uint32_t)ntiles;
-  grid = (unsigned)ntiles;
-  if (ls.queue != nullptr && ls.persistent_wgs != 0 && ntiles > ls.persistent_wgs) {
-    tq.counter = ls.queue + slot;
-    grid = ls.persistent_wgs;
-    return launch_fill_u32(tq.counter, 1, 0u, st);
-  }
+// Compiled lane lengths: the insert's store pass walks 32 (default) or 64
+// k-mers per lane, the query and the insert's repair walk 48 (default) or 32;
+// the non-default lengths exist for the paper's default parameter set only.
+template <int K, int S, int M, int H>
+constexpr bool lane_len_variants() { return K == 31 && S == 28 && M == 16 && H == 4; }
+
+template <int K, int S, int M, int H, int QL>
+hipError_t query_lane_launch(const uint64_t *words, uint32_t shard_mask, const SeqArgs &a, const LaunchShape &ls,
+                             hipStream_t st, int aligned) {
+  const uint64_t tile = (uint64_t)QL * kQueryLaneWG;
+  SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, QL, kQueryLaneWG, kQueryLaneD>), kQueryLaneWG,
+                   (a.n_out + tile - 1) / tile, 2, a.seq, a.len, a.starts, aligned, words, shard_mask, a.out,
+                   a.n_out, (int)(((uintptr_t)a.out & 15u) == 0), a.packed);
   return hipSuccess;
 }
 
-#define SBF_LAUNCH_TILES(KERNEL, WGS, NTILES, SLOT, ...)                      \
-  do {                                                                          \
-    TileQueue tq_;                                                              \
-    unsigned grid_;                                                             \
-    hipError_t e_ = tile_grid((NTILES), ls, (SLOT), st, tq_, grid_);            \
-    if (e_ != hipSuccess) return e_;                                            \
-    hipLaunchKernelGGL(KERNEL, dim3(grid_), dim3(WGS), 0, st, __VA_ARGS__, tq_); \
-    e_ = hipGetLastError();                                                     \
-    if (e_ != hipSuccess) return e_;                                            \
-  } while (0)
+template <int K, int S, int M, int H, int QL>
+hipError_t repair_launch(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, uint64_t nk, const LaunchShape &ls,
+                         hipStream_t st, int aligned) {
+  const uint64_t qtile = (uint64_t)QL * kQueryLaneWG;
+  SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, QL, kQueryLaneWG, kQueryLaneD, true>), kQueryLaneWG,
+                   (nk + qtile - 1) / qtile, 1, a.seq, a.len, a.starts, aligned, words, shard_mask,
+                   (uint8_t *)nullptr, nk, 0, 0);
+  return hipSuccess;
+}
+
+template <int K, int S, int M, int H, int IL>
+hipError_t store_launch(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, uint64_t nk, int mode,
+                        const LaunchShape &ls, hipStream_t st, int aligned) {
+  const uint64_t tile = (uint64_t)IL * kInsertWG;
+  const uint64_t ntiles = (nk + tile - 1) / tile;
+  if (mode == kInsertAtomicMode)
+    SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, IL, kInsertWG, kAtomic>), kInsertWG, ntiles, 0, a.seq,
+                     a.len, a.starts, aligned, words, shard_mask);
+  else
+    SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, IL, kInsertWG, kStore>), kInsertWG, ntiles, 0, a.seq, a.len,
+                     a.starts, aligned, words, shard_mask);
+  return hipSuccess;
+}
 
 template <int K, int S, int M, int H>
 hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, int mode, const LaunchShape &ls,
                           hipStream_t st) {
   if (a.len < (uint64_t)K) return hipSuccess;
   const uint64_t nk = a.len - K + 1;
-  const uint64_t tile = (uint64_t)kInsertL * kInsertWG;
-  const uint64_t ntiles = (nk + tile - 1) / tile;
   const int aligned = ((uintptr_t)a.seq & 15u) == 0;
-  if (mode == kInsertAtomicMode) {
-    SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kAtomic>), kInsertWG, ntiles, 0,
-                     a.seq, a.len, a.starts, aligned, words, shard_mask);
-    return hipSuccess;
+  hipError_t e;
+  if constexpr (lane_len_variants<K, S, M, H>()) {
+    if (ls.insert_lane_len == 64)
+      e = store_launch<K, S, M, H, 64>(words, shard_mask, a, nk, mode, ls, st, aligned);
+    else
+      e = store_launch<K, S, M, H, kInsertL>(words, shard_mask, a, nk, mode, ls, st, aligned);
+  } else {
+    e = store_launch<K, S, M, H, kInsertL>(words, shard_mask, a, nk, mode, ls, st, aligned);
   }
-  SBF_LAUNCH_TILES((insert_rolling_kernel<K, S, M, H, kInsertL, kInsertWG, kStore>), kInsertWG, ntiles, 0, a.seq,
-                   a.len, a.starts, aligned, words, shard_mask);
+  if (e != hipSuccess || mode == kInsertAtomicMode) return e;
   // Repair pass: the lane query walk, OR-ing the bits the store pass lost.
-  const uint64_t qtile = (uint64_t)kQueryLaneL * kQueryLaneWG;
-  SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, kQueryLaneL, kQueryLaneWG, kQueryLaneD, true>), kQueryLaneWG,
-                   (nk + qtile - 1) / qtile, 1, a.seq, a.len, a.starts, aligned, words, shard_mask,
-                   (uint8_t *)nullptr, nk, 0, 0);
-  return hipSuccess;
+  if constexpr (lane_len_variants<K, S, M, H>()) {
+    if (ls.query_lane_len == 32) return repair_launch<K, S, M, H, 32>(words, shard_mask, a, nk, ls, st, aligned);
+  }
+  return repair_launch<K, S, M, H, kQueryLaneL>(words, shard_mask, a, nk, ls, st, aligned);
 }
 
 template <int K, int S, int M, int H>
@@ -815,11 +758,10 @@ hipError_t query_rolling(const uint64_t *words, uint32_t shard_mask, const SeqAr
   if (a.n_out == 0) return hipSuccess;
   const int aligned = ((uintptr_t)a.seq & 15u) == 0;
   if (mode == kQueryLaneMode) {
-    const uint64_t tile = (uint64_t)kQueryLaneL * kQueryLaneWG;
-    SBF_LAUNCH_TILES((query_lane_kernel<K, S, M, H, kQueryLaneL, kQueryLaneWG, kQueryLaneD>), kQueryLaneWG,
-                     (a.n_out + tile - 1) / tile, 2, a.seq, a.len, a.starts, aligned, words, shard_mask, a.out,
-                     a.n_out, (int)(((uintptr_t)a.out & 15u) == 0), a.packed);
-    return hipSuccess;
+    if constexpr (lane_len_variants<K, S, M, H>()) {
+      if (ls.query_lane_len == 32) return query_lane_launch<K, S, M, H, 32>(words, shard_mask, a, ls, st, aligned);
+    }
+    return query_lane_launch<K, S, M, H, kQueryLaneL>(words, shard_mask, a, ls, st, aligned);
   }
   if (a.packed) return hipErrorInvalidValue;  // bits only from the lane organisation
   const uint64_t tile = 16ull * kQueryWG;

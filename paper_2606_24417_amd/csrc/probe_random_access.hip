@@ -29,29 +29,38 @@ __device__ __forceinline__ uint64_t scramble(uint64_t x) {
 // register budget allows two waves per SIMD, so that the compiler keeps every
 // load of a batch in its own registers instead of reusing them (which would
 // serialise the loads on waits).
-template <int MODE, int SB, int D>
+//
+// With COOP (the _LINE modes) the SB/16 consecutive lanes of a group share
+// each shard: lane c of the group loads and stores 16-byte piece c, so one
+// wave instruction covers 64 * 16 / SB whole shards (the access pattern of
+// the wide-shard kernels, which move a super-k-mer's line with SB/16 lanes).
+template <int MODE, int SB, int D, bool COOP = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void random_shards(uint64_t *__restrict__ buf, uint64_t shard_mask,
                                                         uint64_t seed, uint32_t batches,
                                                         uint64_t *__restrict__ sink) {
-  constexpr int C = SB / 16;  // 16-byte chunks per shard
+  constexpr int P = COOP ? SB / 16 : 1;  // lanes per shard
+  constexpr int C = SB / 16 / P;         // 16-byte chunks per lane and shard
   const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const uint64_t nthreads = (uint64_t)gridDim.x * kBlock;
+  const uint64_t group = tid / P, ngroups = nthreads / P;
+  const int piece = (int)(tid % P);
   uint64_t acc = 0;
   for (uint32_t it = 0; it < batches; ++it) {
     uint64_t idx[D];
     uint64_t bit[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const uint64_t op = ((uint64_t)it * nthreads + tid) * D + (uint64_t)d;
+      const uint64_t op = ((uint64_t)it * ngroups + group) * D + (uint64_t)d;
       const uint64_t h = scramble(op * 0x9E3779B97F4A7C15ull + seed);
       idx[d] = h & shard_mask;
       bit[d] = 1ull << (h >> 58);
     }
-    if constexpr (MODE == SBF_PROBE_READ || MODE == SBF_PROBE_RMW) {
+    if constexpr (MODE == SBF_PROBE_READ || MODE == SBF_PROBE_RMW || MODE == SBF_PROBE_READ_LINE ||
+                  MODE == SBF_PROBE_RMW_LINE) {
       uint4 v[D][C];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const uint4 *q = reinterpret_cast<const uint4 *>(buf + idx[d] * (SB / 8));
+        const uint4 *q = reinterpret_cast<const uint4 *>(buf + idx[d] * (SB / 8)) + piece;
 #pragma unroll
         for (int c = 0; c < C; ++c) v[d][c] = q[c];
       }
@@ -64,7 +73,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       for (int d = 0; d < D; ++d)
 #pragma unroll
         for (int c = 0; c < C; ++c) asm volatile("" : "+v"(v[d][c].x), "+v"(v[d][c].y), "+v"(v[d][c].z), "+v"(v[d][c].w));
-      if constexpr (MODE == SBF_PROBE_READ) {
+      if constexpr (MODE == SBF_PROBE_READ || MODE == SBF_PROBE_READ_LINE) {
 #pragma unroll
         for (int d = 0; d < D; ++d)
 #pragma unroll
@@ -74,7 +83,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
         for (int d = 0; d < D; ++d) {
           v[d][0].x |= (uint32_t)bit[d];
           v[d][C - 1].w |= (uint32_t)(bit[d] >> 32);
-          uint4 *q = reinterpret_cast<uint4 *>(buf + idx[d] * (SB / 8));
+          uint4 *q = reinterpret_cast<uint4 *>(buf + idx[d] * (SB / 8)) + piece;
 #pragma unroll
           for (int c = 0; c < C; ++c) q[c] = v[d][c];
         }
@@ -92,7 +101,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
     }
   }
-  if (MODE == SBF_PROBE_READ && acc == 0x5bd1e995ull) sink[0] = acc;  // keeps the loads
+  if ((MODE == SBF_PROBE_READ || MODE == SBF_PROBE_READ_LINE) && acc == 0x5bd1e995ull) sink[0] = acc;  // keeps the loads
 }
 
 __global__ __launch_bounds__(kBlock) void stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
@@ -116,10 +125,11 @@ template <int MODE>
 hipError_t launch_random(uint64_t *buf, uint64_t bytes, uint32_t sb, uint32_t d, unsigned grid, uint32_t batches,
                          uint64_t seed, uint64_t *sink) {
   const uint64_t mask = bytes / sb - 1;
+  constexpr bool coop = MODE == SBF_PROBE_READ_LINE || MODE == SBF_PROBE_RMW_LINE;
 #define SBF_PROBE_CASE(SB_, D_)                                                                              \
   if (sb == SB_ && d == D_) {                                                                                \
-    hipLaunchKernelGGL((random_shards<MODE, SB_, D_>), dim3(grid), dim3(kBlock), 0, 0, buf, mask, seed, batches, \
-                       sink);                                                                                \
+    hipLaunchKernelGGL((random_shards<MODE, SB_, D_, coop>), dim3(grid), dim3(kBlock), 0, 0, buf, mask, seed,    \
+                       batches, sink);                                                                       \
     return hipGetLastError();                                                                                \
   }
   SBF_PROBE_CASE(32, 1) SBF_PROBE_CASE(32, 4) SBF_PROBE_CASE(32, 8) SBF_PROBE_CASE(32, 16)
@@ -141,6 +151,8 @@ hipError_t launch(int mode, uint64_t *buf, uint64_t bytes, uint32_t sb, uint32_t
     case SBF_PROBE_READ: return launch_random<SBF_PROBE_READ>(buf, bytes, sb, d, grid, batches, seed, sink);
     case SBF_PROBE_RMW: return launch_random<SBF_PROBE_RMW>(buf, bytes, sb, d, grid, batches, seed, sink);
     case SBF_PROBE_ATOMIC4: return launch_random<SBF_PROBE_ATOMIC4>(buf, bytes, sb, d, grid, batches, seed, sink);
+    case SBF_PROBE_READ_LINE: return launch_random<SBF_PROBE_READ_LINE>(buf, bytes, sb, d, grid, batches, seed, sink);
+    case SBF_PROBE_RMW_LINE: return launch_random<SBF_PROBE_RMW_LINE>(buf, bytes, sb, d, grid, batches, seed, sink);
     default: return launch_random<SBF_PROBE_ATOMIC1>(buf, bytes, sb, d, grid, batches, seed, sink);
   }
 }
@@ -232,7 +244,7 @@ extern "C" int sbf_probe_valu(int op, double *wave_instr_per_second, double *ms)
 
 extern "C" int sbf_probe_random_access(uint64_t bytes, int mode, uint32_t shard_bytes, uint32_t inflight,
                                        uint32_t wgs_per_cu, uint64_t ops, double *per_second, double *ms) {
-  if (!per_second || !ms || mode < SBF_PROBE_READ || mode > SBF_PROBE_COPY) return -1;
+  if (!per_second || !ms || mode < SBF_PROBE_READ || mode > SBF_PROBE_RMW_LINE) return -1;
   if (bytes < (1ull << 16) || bytes > (1ull << 36) || (bytes & (bytes - 1))) return -1;
   if (mode != SBF_PROBE_COPY && (!depth_supported(shard_bytes, inflight) || wgs_per_cu < 1 || wgs_per_cu > 16))
     return -1;
@@ -241,7 +253,10 @@ extern "C" int sbf_probe_random_access(uint64_t bytes, int mode, uint32_t shard_
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     return -3;
   const unsigned grid = (unsigned)cus * wgs_per_cu;
-  const uint64_t per_batch = (uint64_t)grid * kBlock * (mode == SBF_PROBE_COPY ? 1 : inflight);
+  // shard operations per batch of the grid (a shard per SB/16 lanes in the _LINE modes)
+  const uint64_t lanes_per_shard =
+      (mode == SBF_PROBE_READ_LINE || mode == SBF_PROBE_RMW_LINE) ? (uint64_t)shard_bytes / 16 : 1;
+  const uint64_t per_batch = (uint64_t)grid * kBlock * (mode == SBF_PROBE_COPY ? 1 : inflight) / lanes_per_shard;
   if (ops < (1ull << 20)) ops = 1ull << 20;
   const uint64_t nb = (ops + per_batch - 1) / per_batch;
   if (nb > 0xffffffffull) return -1;

@@ -110,6 +110,9 @@ struct sbf_filter {
   // (4 measured best for both kernels on MI355X)
   uint32_t insert_wgs_per_cu = 4;
   uint32_t query_wgs_per_cu = 4;
+  // k-mers per lane of the insert and query tiles (0: the family's default)
+  uint32_t insert_lane_len = 0;
+  uint32_t query_lane_len = 0;
   int num_cus = 1;
   uint64_t staging = kDefaultStaging;
   // host entry points: chunk pipeline (created on first use)
@@ -129,9 +132,48 @@ uint64_t next_pow2(uint64_t x) {
   return n;
 }
 
-bool use_rolling(const sbf_filter *f) {
-  if (f->variant == SBF_VARIANT_GENERIC) return false;
-  return sbf::rolling_supported(f->g);
+// Kernel family a filter's launches use: the 4-word lane kernels, the
+// wide-shard kernels (any of 4, 8, 16 words) or the generic kernels.
+enum Family { kGenericFamily, kLaneFamily, kWideFamily };
+
+Family family(const sbf_filter *f) {
+  switch (f->variant) {
+    case SBF_VARIANT_GENERIC:
+      return kGenericFamily;
+    case SBF_VARIANT_WIDE:
+      return sbf::wide_supported(f->g) ? kWideFamily : kGenericFamily;
+    default:  // AUTO and ROLLING: the super-k-mer kernels compiled for the filter
+      if (sbf::rolling_supported(f->g)) return kLaneFamily;
+      if (sbf::wide_supported(f->g)) return kWideFamily;
+      return kGenericFamily;
+  }
+}
+
+bool use_rolling(const sbf_filter *f) { return family(f) != kGenericFamily; }
+
+// Compiled k-mers per lane of each family (0 stands for the default).
+bool lane_len_ok(const sbf_filter *f, uint32_t n, bool insert) {
+  if (n == 0) return true;
+  switch (family(f)) {
+    case kLaneFamily: {
+      const Geometry &g = f->g;
+      if (!(g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4)) return false;
+      return insert ? (n == 32 || n == 64) : (n == 32 || n == 48);
+    }
+    case kWideFamily:
+      return n == 16 || n == 32;
+    default:
+      return false;
+  }
+}
+
+uint32_t lane_len_effective(const sbf_filter *f, uint32_t n, bool insert) {
+  if (n) return n;
+  switch (family(f)) {
+    case kLaneFamily: return insert ? 32 : 48;
+    case kWideFamily: return 16;
+    default: return 0;
+  }
 }
 
 // stream-ordered entry points run on the caller's stream; NULL is HIP's null stream
@@ -206,7 +248,10 @@ int run_insert(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::Launc
       int rc = launch_shape(f, f->insert_wgs_per_cu, st, ls);
       if (rc) return rc;
     }
-    e = sbf::launch_insert_rolling(f->g, f->words, a, mode, ls, st);
+    ls.insert_lane_len = f->insert_lane_len;
+    ls.query_lane_len = f->query_lane_len;
+    e = family(f) == kWideFamily ? sbf::launch_insert_wide(f->g, f->words, a, mode, ls, st)
+                                 : sbf::launch_insert_rolling(f->g, f->words, a, mode, ls, st);
   } else {
     e = sbf::launch_insert_generic(f->g, f->words, a, st);
   }
@@ -232,7 +277,10 @@ int run_query(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::Launch
       int rc = launch_shape(f, f->query_wgs_per_cu, st, ls);
       if (rc) return rc;
     }
-    e = sbf::launch_query_rolling(f->g, f->words, a, mode, ls, st);
+    ls.insert_lane_len = f->insert_lane_len;
+    ls.query_lane_len = f->query_lane_len;
+    e = family(f) == kWideFamily ? sbf::launch_query_wide(f->g, f->words, a, ls, st)
+                                 : sbf::launch_query_rolling(f->g, f->words, a, mode, ls, st);
   } else {
     e = sbf::launch_query_generic(f->g, f->words, a, st);
   }
@@ -469,7 +517,7 @@ int host_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_t nre
   const uint64_t k = f->g.k;
   const uint64_t total = off[nrec];
   const uint64_t budget = std::max<uint64_t>(f->staging, 4096);
-  const bool packed = query && use_rolling(f) && sbf::query_packed_supported(query_kernel_mode(f));
+  const bool packed = query && family(f) == kLaneFamily && sbf::query_packed_supported(query_kernel_mode(f));
   // k-mer starts per chunk; a multiple of 64 when answers travel as bits, so
   // that every chunk's bits start on a byte
   const uint64_t span = packed ? (budget - (k - 1)) & ~63ull : budget - (k - 1);
@@ -687,6 +735,30 @@ int sbf_clear(sbf_filter *f, void *stream) {
   return ok();
 }
 
+int sbf_estimate_fpr(const sbf_filter *f, double *fpr, uint64_t *set_bits) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (!fpr && !set_bits) return set_error(SBF_E_INVAL, "no output");
+  if ((rc = set_device(f))) return rc;
+  SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
+  Scratch acc;
+  if ((rc = grow(acc, 16, "statistics accumulators"))) return rc;
+  double *d_sum = (double *)acc.ptr;
+  uint64_t *d_bits = (uint64_t *)acc.ptr + 1;
+  hipError_t e = sbf::launch_fill_u64((uint64_t *)acc.ptr, 2, 0ull, f->stream);
+  if (e == hipSuccess) e = sbf::launch_estimate_fpr(f->g, f->words, d_sum, d_bits, f->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(f->stream);
+  uint64_t host[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpy(host, acc.ptr, 16, hipMemcpyDeviceToHost);
+  (void)hipFree(acc.ptr);
+  if (e != hipSuccess) return hip_error(e, "filter statistics");
+  double sum;
+  memcpy(&sum, &host[0], sizeof sum);
+  if (fpr) *fpr = sum / (double)f->g.nshards;
+  if (set_bits) *set_bits = host[1];
+  return ok();
+}
+
 int sbf_insert_seq_dev(sbf_filter *f, const char *d_seq, uint64_t len, void *stream) {
   int rc;
   if ((rc = check_filter(f))) return rc;
@@ -853,18 +925,48 @@ int sbf_query_batch(sbf_filter *f, const char *seq, const uint64_t *off, uint64_
 int sbf_set_variant(sbf_filter *f, int variant) {
   int rc;
   if ((rc = check_filter(f))) return rc;
-  if (variant == SBF_VARIANT_ROLLING && !sbf::rolling_supported(f->g))
-    return set_error(SBF_E_INVAL, "no rolling kernel for k=%u s=%u m=%u H=%u", f->g.k, f->g.s, f->g.m, f->g.H);
-  if (variant != SBF_VARIANT_AUTO && variant != SBF_VARIANT_ROLLING && variant != SBF_VARIANT_GENERIC)
+  if (variant != SBF_VARIANT_AUTO && variant != SBF_VARIANT_ROLLING && variant != SBF_VARIANT_GENERIC &&
+      variant != SBF_VARIANT_WIDE)
     return set_error(SBF_E_INVAL, "unknown variant %d", variant);
+  if (variant == SBF_VARIANT_ROLLING && !sbf::rolling_supported(f->g) && !sbf::wide_supported(f->g))
+    return set_error(SBF_E_INVAL, "no rolling kernel for k=%u s=%u m=%u H=%u with %u-word shards", f->g.k, f->g.s,
+                     f->g.m, f->g.H, f->g.shard_words);
+  if (variant == SBF_VARIANT_WIDE && !sbf::wide_supported(f->g))
+    return set_error(SBF_E_INVAL, "no wide-shard kernel for k=%u s=%u m=%u H=%u", f->g.k, f->g.s, f->g.m, f->g.H);
   f->variant = variant;
+  // lane lengths belong to a family: back to the new family's defaults
+  f->insert_lane_len = 0;
+  f->query_lane_len = 0;
   return ok();
 }
 
 int sbf_get_variant(const sbf_filter *f) {
   if (!f) return set_error(SBF_E_INVAL, "filter is NULL");
   ok();
-  return use_rolling(f) ? SBF_VARIANT_ROLLING : SBF_VARIANT_GENERIC;
+  switch (family(f)) {
+    case kLaneFamily: return SBF_VARIANT_ROLLING;
+    case kWideFamily: return SBF_VARIANT_WIDE;
+    default: return SBF_VARIANT_GENERIC;
+  }
+}
+
+int sbf_set_tile(sbf_filter *f, uint32_t insert_kmers_per_lane, uint32_t query_kmers_per_lane) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (!lane_len_ok(f, insert_kmers_per_lane, true) || !lane_len_ok(f, query_kmers_per_lane, false))
+    return set_error(SBF_E_INVAL, "no compiled tile of %u (insert) / %u (query) k-mers per lane for this filter",
+                     insert_kmers_per_lane, query_kmers_per_lane);
+  f->insert_lane_len = insert_kmers_per_lane;
+  f->query_lane_len = query_kmers_per_lane;
+  return ok();
+}
+
+int sbf_get_tile(const sbf_filter *f, uint32_t *insert_kmers_per_lane, uint32_t *query_kmers_per_lane) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  if (insert_kmers_per_lane) *insert_kmers_per_lane = lane_len_effective(f, f->insert_lane_len, true);
+  if (query_kmers_per_lane) *query_kmers_per_lane = lane_len_effective(f, f->query_lane_len, false);
+  return ok();
 }
 
 int sbf_set_insert_mode(sbf_filter *f, int mode) {
@@ -1052,137 +1154,333 @@ void sbf_graph_destroy(sbf_graph *g) {
   graph_release(g);
 }
 
-int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec,
-                 const char *d_q, uint64_t q_len, const uint64_t *d_q_off, uint64_t q_nrec, char *report,
-                 uint64_t report_len) {
-  int rc;
-  if ((rc = check_filter(f))) return rc;
-  if (!d_ins || !d_ins_off || !ins_len || !ins_nrec || !d_q || !d_q_off || !q_len || !q_nrec)
-    return set_error(SBF_E_INVAL, "autotuning needs an insert batch and a query batch");
-  if ((rc = set_device(f))) return rc;
-  std::string rep;
-#define line(...) appendf(rep, __VA_ARGS__)
-  if (!use_rolling(f)) {
-    line("generic kernels: nothing to tune\n");
-  } else {
-    // The trials run on the filter itself, so that they see its own memory
-    // (a second filter-sized allocation can be mapped differently and time
-    // differently out of cache); its words are saved first and put back after.
-    sbf_filter *t = f;
-    Scratch si, sq, out, saved;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipStream_t st = t->stream;
-    const int keep_imode = f->insert_mode, keep_qmode = f->query_mode;
-    const uint32_t keep_iw = f->insert_wgs_per_cu, keep_qw = f->query_wgs_per_cu;
-    SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
-    bool backed_up = false;
-    rc = grow(saved, sbf_num_words(f) * sizeof(uint64_t), "filter backup");
-    if (!rc) {
-      if (hipMemcpyAsync(saved.ptr, f->words, sbf_num_words(f) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st) ==
-          hipSuccess)
-        backed_up = true;
-      else
-        rc = set_error(SBF_E_DEVICE, "filter backup copy");
-    }
-    if (!rc) rc = grow(si, (ins_len + 31) / 32 * 4, "record-start bits");
-    if (!rc) rc = grow(sq, (q_len + 31) / 32 * 4, "record-start bits");
-    if (!rc) rc = grow(out, q_len, "autotune answers");
-    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
-      rc = set_error(SBF_E_DEVICE, "event creation");
-    const uint32_t *st_i = nullptr, *st_q = nullptr;
-    if (!rc) rc = mark_into(si, d_ins_off, ins_nrec, ins_len, st, &st_i);
-    if (!rc) rc = mark_into(sq, d_q_off, q_nrec, q_len, st, &st_q);
-    const uint32_t shapes[] = {0, 1, 2, 4, 8};
-    auto time_it = [&](bool insert, float &ms_out) -> int {
-      float best[3];
-      for (int rep_i = 0; rep_i < 4; ++rep_i) {
-        if (insert) {
-          hipError_t e = sbf::launch_fill_u64(t->words, sbf_num_words(t), 0ull, st);
-          if (e != hipSuccess) return hip_error(e, "clear kernel launch");
-        }
-        if (hipEventRecord(e0, st) != hipSuccess) return set_error(SBF_E_DEVICE, "event record");
-        int r2 = insert ? run_insert(t, SeqArgs{(const uint8_t *)d_ins, ins_len, st_i, nullptr, 0}, st)
-                        : run_query(t, SeqArgs{(const uint8_t *)d_q, q_len, st_q, (uint8_t *)out.ptr, q_len}, st);
-        if (r2) return r2;
-        float ms = 0.f;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-          return set_error(SBF_E_DEVICE, "event timing");
-        if (rep_i > 0) best[rep_i - 1] = ms;
-      }
-      std::sort(best, best + 3);
-      ms_out = best[1];
-      return SBF_OK;
-    };
-    float best_ins = 1e30f, best_q = 1e30f;
-    int bi_mode = SBF_INSERT_TWO_PASS, bq_mode = SBF_QUERY_LANE;
-    uint32_t bi_shape = 0, bq_shape = 0;
-    for (int mode : {SBF_INSERT_TWO_PASS, SBF_INSERT_ATOMIC}) {
-      for (uint32_t sh : shapes) {
-        if (rc) break;
-        t->insert_mode = mode;
-        t->insert_wgs_per_cu = sh;
-        float ms;
-        rc = time_it(true, ms);
-        if (rc) break;
-        line("insert %-8s workgroups/CU %u%s: %.4f ms\n", mode == SBF_INSERT_ATOMIC ? "atomic" : "two-pass", sh,
-             sh ? "" : " (one per tile)", ms);
-        if (ms < best_ins) {
-          best_ins = ms;
-          bi_mode = mode;
-          bi_shape = sh;
-        }
-      }
-    }
-    for (int mode : {SBF_QUERY_LANE, SBF_QUERY_LEADER, SBF_QUERY_DIRECT}) {
-      for (uint32_t sh : shapes) {
-        if (rc) break;
-        t->query_mode = mode;
-        t->query_wgs_per_cu = sh;
-        float ms;
-        rc = time_it(false, ms);
-        if (rc) break;
-        line("query  %-8s workgroups/CU %u%s: %.4f ms\n",
-             mode == SBF_QUERY_LANE ? "lane" : mode == SBF_QUERY_LEADER ? "leader" : "direct", sh,
-             sh ? "" : " (one per tile)", ms);
-        if (ms < best_q) {
-          best_q = ms;
-          bq_mode = mode;
-          bq_shape = sh;
-        }
-      }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    // put the filter's words back
-    if (backed_up && hipMemcpyAsync(f->words, saved.ptr, sbf_num_words(f) * sizeof(uint64_t),
-                                    hipMemcpyDeviceToDevice, st) != hipSuccess && !rc)
-      rc = set_error(SBF_E_DEVICE, "filter restore copy");
-    (void)hipStreamSynchronize(st);
-    free_scratch(si);
-    free_scratch(sq);
-    free_scratch(out);
-    free_scratch(saved);
-    f->insert_mode = keep_imode;
-    f->query_mode = keep_qmode;
-    f->insert_wgs_per_cu = keep_iw;
-    f->query_wgs_per_cu = keep_qw;
-    if (rc) return rc;
-    f->insert_mode = bi_mode;
-    f->insert_wgs_per_cu = bi_shape;
-    f->query_mode = bq_mode;
-    f->query_wgs_per_cu = bq_shape;
-    line("best insert: %s, workgroups/CU %u (%.4f ms)\n", bi_mode == SBF_INSERT_ATOMIC ? "atomic" : "two-pass",
-         bi_shape, best_ins);
-    line("best query: %s, workgroups/CU %u (%.4f ms)\n",
-         bq_mode == SBF_QUERY_LANE ? "lane" : bq_mode == SBF_QUERY_LEADER ? "leader" : "direct", bq_shape, best_q);
-  }
-#undef line
+}  // extern "C"
+
+namespace {
+
+void copy_report(const std::string &rep, char *report, uint64_t report_len) {
   if (report && report_len) {
     const size_t n = std::min<size_t>(rep.size(), report_len - 1);
     memcpy(report, rep.data(), n);
     report[n] = 0;
   }
+}
+
+struct Batch {
+  const char *seq;
+  uint64_t len;
+  const uint64_t *off;
+  uint64_t nrec;
+  bool ok() const { return seq && off && len && nrec; }
+};
+
+// Autotuner of one filter: on the insert batch `ins` and query batch `q`,
+// time every insert strategy, query organisation, compiled lane length and
+// launch shape of the filter's kernel family (median of three runs after a
+// warm-up) on f itself, whose words are saved to a temporary device buffer
+// and restored afterwards, then apply the fastest.  Generic kernels have
+// nothing to tune and are timed as they are.  Appends the report to rep and
+// returns the best insert and query times.
+int autotune_filter(sbf_filter *f, const Batch &ins, const Batch &q, std::string &rep, float *best_ins_out,
+                    float *best_q_out) {
+  int rc = SBF_OK;
+#define line(...) appendf(rep, __VA_ARGS__)
+  // The trials run on the filter itself, so that they see its own memory (a
+  // second filter-sized allocation can be mapped differently and time
+  // differently out of cache); its words are saved first and put back after.
+  sbf_filter *t = f;
+  Scratch si, sq, out, saved;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t st = t->stream;
+  const int keep_imode = f->insert_mode, keep_qmode = f->query_mode;
+  const uint32_t keep_iw = f->insert_wgs_per_cu, keep_qw = f->query_wgs_per_cu;
+  const uint32_t keep_il = f->insert_lane_len, keep_ql = f->query_lane_len;
+  SBF_HIP(hipDeviceSynchronize(), "device synchronisation");
+  bool backed_up = false;
+  rc = grow(saved, sbf_num_words(f) * sizeof(uint64_t), "filter backup");
+  if (!rc) {
+    if (hipMemcpyAsync(saved.ptr, f->words, sbf_num_words(f) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st) ==
+        hipSuccess)
+      backed_up = true;
+    else
+      rc = set_error(SBF_E_DEVICE, "filter backup copy");
+  }
+  if (!rc) rc = grow(si, (ins.len + 31) / 32 * 4, "record-start bits");
+  if (!rc) rc = grow(sq, (q.len + 31) / 32 * 4, "record-start bits");
+  if (!rc) rc = grow(out, q.len, "autotune answers");
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = set_error(SBF_E_DEVICE, "event creation");
+  const uint32_t *st_i = nullptr, *st_q = nullptr;
+  if (!rc) rc = mark_into(si, ins.off, ins.nrec, ins.len, st, &st_i);
+  if (!rc) rc = mark_into(sq, q.off, q.nrec, q.len, st, &st_q);
+  auto time_it = [&](bool insert, float &ms_out) -> int {
+    float best[3];
+    for (int rep_i = 0; rep_i < 4; ++rep_i) {
+      if (insert) {
+        hipError_t e = sbf::launch_fill_u64(t->words, sbf_num_words(t), 0ull, st);
+        if (e != hipSuccess) return hip_error(e, "clear kernel launch");
+      }
+      if (hipEventRecord(e0, st) != hipSuccess) return set_error(SBF_E_DEVICE, "event record");
+      int r2 = insert ? run_insert(t, SeqArgs{(const uint8_t *)ins.seq, ins.len, st_i, nullptr, 0}, st)
+                      : run_query(t, SeqArgs{(const uint8_t *)q.seq, q.len, st_q, (uint8_t *)out.ptr, q.len}, st);
+      if (r2) return r2;
+      float ms = 0.f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return set_error(SBF_E_DEVICE, "event timing");
+      if (rep_i > 0) best[rep_i - 1] = ms;
+    }
+    std::sort(best, best + 3);
+    ms_out = best[1];
+    return SBF_OK;
+  };
+  float best_ins = 1e30f, best_q = 1e30f;
+  int bi_mode = f->insert_mode, bq_mode = f->query_mode;
+  uint32_t bi_shape = f->insert_wgs_per_cu, bq_shape = f->query_wgs_per_cu, bi_len = 0, bq_len = 0;
+  const Family fam = family(f);
+  if (fam == kGenericFamily) {
+    if (!rc) rc = time_it(true, best_ins);
+    if (!rc) rc = time_it(false, best_q);
+    if (!rc) line("generic kernels (nothing to tune): insert %.4f ms, query %.4f ms\n", best_ins, best_q);
+  } else {
+    const bool wide = fam == kWideFamily;
+    const uint32_t shapes[] = {0, 1, 2, 4, 8};
+    // compiled k-mers per lane (the tile is 256 lanes of them)
+    std::vector<uint32_t> ins_lens, q_lens;
+    for (uint32_t n : {16u, 32u, 48u, 64u}) {
+      if (lane_len_ok(f, n, true)) ins_lens.push_back(n);
+      if (lane_len_ok(f, n, false)) q_lens.push_back(n);
+    }
+    if (ins_lens.empty()) ins_lens.push_back(0);
+    if (q_lens.empty()) q_lens.push_back(0);
+    // the insert's repair walk runs at the query's default lane length here
+    t->query_lane_len = 0;
+    for (int mode : {SBF_INSERT_TWO_PASS, SBF_INSERT_ATOMIC}) {
+      for (uint32_t len : ins_lens) {
+        for (uint32_t sh : shapes) {
+          if (rc) break;
+          t->insert_mode = mode;
+          t->insert_wgs_per_cu = sh;
+          t->insert_lane_len = len;
+          float ms;
+          rc = time_it(true, ms);
+          if (rc) break;
+          line("insert %-8s %2u k-mers/lane, workgroups/CU %u%s: %.4f ms\n",
+               mode == SBF_INSERT_ATOMIC ? "atomic" : "two-pass", lane_len_effective(t, len, true), sh,
+               sh ? "" : " (one per tile)", ms);
+          if (ms < best_ins) {
+            best_ins = ms;
+            bi_mode = mode;
+            bi_shape = sh;
+            bi_len = len;
+          }
+        }
+      }
+    }
+    t->insert_lane_len = 0;
+    for (int mode : {SBF_QUERY_LANE, SBF_QUERY_LEADER, SBF_QUERY_DIRECT}) {
+      // the wide-shard kernels have one query organisation; lane lengths
+      // apply to the lane-sequential query and to the wide kernels
+      if (wide && mode != SBF_QUERY_LANE) continue;
+      for (uint32_t len : q_lens) {
+        if (mode != SBF_QUERY_LANE && len != q_lens[0]) continue;
+        for (uint32_t sh : shapes) {
+          if (rc) break;
+          t->query_mode = mode;
+          t->query_wgs_per_cu = sh;
+          t->query_lane_len = mode == SBF_QUERY_LANE ? len : 0;
+          float ms;
+          rc = time_it(false, ms);
+          if (rc) break;
+          line("query  %-8s %2u k-mers/lane, workgroups/CU %u%s: %.4f ms\n",
+               wide ? "wide" : mode == SBF_QUERY_LANE ? "lane" : mode == SBF_QUERY_LEADER ? "leader" : "direct",
+               mode == SBF_QUERY_LANE ? lane_len_effective(t, len, false) : 16u, sh, sh ? "" : " (one per tile)",
+               ms);
+          if (ms < best_q) {
+            best_q = ms;
+            bq_mode = mode;
+            bq_shape = sh;
+            bq_len = mode == SBF_QUERY_LANE ? len : 0;
+          }
+        }
+      }
+    }
+    if (!rc) {
+      line("best insert: %s, %u k-mers/lane, workgroups/CU %u (%.4f ms)\n",
+           bi_mode == SBF_INSERT_ATOMIC ? "atomic" : "two-pass", lane_len_effective(f, bi_len, true), bi_shape,
+           best_ins);
+      line("best query: %s, %u k-mers/lane, workgroups/CU %u (%.4f ms)\n",
+           wide ? "wide" : bq_mode == SBF_QUERY_LANE ? "lane" : bq_mode == SBF_QUERY_LEADER ? "leader" : "direct",
+           bq_mode == SBF_QUERY_LANE ? lane_len_effective(f, bq_len, false) : 16u, bq_shape, best_q);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  // put the filter's words back
+  if (backed_up && hipMemcpyAsync(f->words, saved.ptr, sbf_num_words(f) * sizeof(uint64_t), hipMemcpyDeviceToDevice,
+                                  st) != hipSuccess && !rc)
+    rc = set_error(SBF_E_DEVICE, "filter restore copy");
+  (void)hipStreamSynchronize(st);
+  free_scratch(si);
+  free_scratch(sq);
+  free_scratch(out);
+  free_scratch(saved);
+  f->insert_mode = keep_imode;
+  f->query_mode = keep_qmode;
+  f->insert_wgs_per_cu = keep_iw;
+  f->query_wgs_per_cu = keep_qw;
+  f->insert_lane_len = keep_il;
+  f->query_lane_len = keep_ql;
+  if (rc) return rc;
+  f->insert_mode = bi_mode;
+  f->insert_wgs_per_cu = bi_shape;
+  f->insert_lane_len = bi_len;
+  f->query_mode = bq_mode;
+  f->query_wgs_per_cu = bq_shape;
+  f->query_lane_len = bq_len;
+  if (best_ins_out) *best_ins_out = best_ins;
+  if (best_q_out) *best_q_out = best_q;
+#undef line
+  return SBF_OK;
+}
+
+// Number of k-mers of batch q that f answers present (nonzero answer bytes,
+// counted on the device); synchronous on f's stream.
+int count_present(sbf_filter *f, const Batch &q, uint64_t *present) {
+  hipStream_t st = f->stream;
+  Scratch starts, out, cnt;
+  int rc = grow(starts, (q.len + 31) / 32 * 4, "record-start bits");
+  if (!rc) rc = grow(out, q.len, "answers");
+  if (!rc) rc = grow(cnt, 8, "counter");
+  const uint32_t *st_q = nullptr;
+  if (!rc) rc = mark_into(starts, q.off, q.nrec, q.len, st, &st_q);
+  hipError_t e = hipSuccess;
+  if (!rc) {
+    e = sbf::launch_fill_u64((uint64_t *)cnt.ptr, 1, 0ull, st);
+    if (e != hipSuccess) rc = hip_error(e, "fill kernel launch");
+  }
+  if (!rc) rc = run_query(f, SeqArgs{(const uint8_t *)q.seq, q.len, st_q, (uint8_t *)out.ptr, q.len}, st);
+  if (!rc) {
+    e = sbf::launch_count_nonzero_u8((const uint8_t *)out.ptr, q.len, (uint64_t *)cnt.ptr, st);
+    if (e != hipSuccess) rc = hip_error(e, "count kernel launch");
+  }
+  (void)hipStreamSynchronize(st);
+  uint64_t host = 0;
+  if (!rc && hipMemcpy(&host, cnt.ptr, 8, hipMemcpyDeviceToHost) != hipSuccess)
+    rc = set_error(SBF_E_DEVICE, "counter copy");
+  free_scratch(starts);
+  free_scratch(out);
+  free_scratch(cnt);
+  *present = host;
+  return rc;
+}
+
+// Insert batch b into f (cleared first); synchronous on f's stream.
+int fill_filter(sbf_filter *f, const Batch &b) {
+  hipStream_t st = f->stream;
+  Scratch starts;
+  hipError_t e = sbf::launch_fill_u64(f->words, sbf_num_words(f), 0ull, st);
+  if (e != hipSuccess) return hip_error(e, "clear kernel launch");
+  int rc = grow(starts, (b.len + 31) / 32 * 4, "record-start bits");
+  const uint32_t *st_i = nullptr;
+  if (!rc) rc = mark_into(starts, b.off, b.nrec, b.len, st, &st_i);
+  if (!rc) rc = run_insert(f, SeqArgs{(const uint8_t *)b.seq, b.len, st_i, nullptr, 0}, st);
+  (void)hipStreamSynchronize(st);
+  free_scratch(starts);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sbf_autotune(sbf_filter *f, const char *d_ins, uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec,
+                 const char *d_q, uint64_t q_len, const uint64_t *d_q_off, uint64_t q_nrec, char *report,
+                 uint64_t report_len) {
+  int rc;
+  if ((rc = check_filter(f))) return rc;
+  const Batch ins{d_ins, ins_len, d_ins_off, ins_nrec}, q{d_q, q_len, d_q_off, q_nrec};
+  if (!ins.ok() || !q.ok()) return set_error(SBF_E_INVAL, "autotuning needs an insert batch and a query batch");
+  if ((rc = set_device(f))) return rc;
+  std::string rep;
+  rc = autotune_filter(f, ins, q, rep, nullptr, nullptr);
+  copy_report(rep, report, report_len);
+  if (rc) return rc;
+  return ok();
+}
+
+int sbf_autotune_geometry(uint32_t k, uint32_t s, uint32_t m, uint32_t H, uint64_t bits, const char *d_ins,
+                          uint64_t ins_len, const uint64_t *d_ins_off, uint64_t ins_nrec, const char *d_q,
+                          uint64_t q_len, const uint64_t *d_q_off, uint64_t q_nrec, const char *d_neg,
+                          uint64_t neg_len, const uint64_t *d_neg_off, uint64_t neg_nrec, double max_fpr,
+                          uint32_t *shard_words, uint32_t *insert_kmers_per_lane, uint32_t *query_kmers_per_lane,
+                          double *fpr, char *report, uint64_t report_len) {
+  const Batch ins{d_ins, ins_len, d_ins_off, ins_nrec}, q{d_q, q_len, d_q_off, q_nrec},
+      neg{d_neg, neg_len, d_neg_off, neg_nrec};
+  if (!ins.ok() || !q.ok() || !neg.ok())
+    return set_error(SBF_E_INVAL, "geometry autotuning needs insert, query and negative batches");
+  if (!shard_words) return set_error(SBF_E_INVAL, "shard_words is NULL");
+  std::string rep;
+  struct Choice {
+    uint32_t S = 0, il = 0, ql = 0;
+    double fpr = 2.0, ms = 1e30;
+  } best_ok, best_any;
+  int rc = SBF_OK;
+  for (uint32_t S : {4u, 8u, 16u}) {
+    sbf_filter *f = sbf_create_ex(k, s, m, H, bits, S);
+    if (!f) {
+      if (g_err == SBF_E_INVAL) {  // this geometry does not exist for H
+        appendf(rep, "shard %2u words: not available for H=%u\n", S, H);
+        continue;
+      }
+      rc = g_err;
+      break;
+    }
+    float ti = 0.f, tq = 0.f;
+    std::string sub;
+    rc = autotune_filter(f, ins, q, sub, &ti, &tq);
+    uint64_t valid = 0, present = 0;
+    // valid k-mers of the negatives: every one is present in a full filter
+    if (!rc) {
+      hipError_t e = sbf::launch_fill_u64(f->words, sbf_num_words(f), ~0ull, f->stream);
+      rc = e == hipSuccess ? count_present(f, neg, &valid) : hip_error(e, "fill kernel launch");
+    }
+    if (!rc) rc = fill_filter(f, ins);
+    if (!rc) rc = count_present(f, neg, &present);
+    uint32_t il = 0, ql = 0;
+    if (!rc) rc = sbf_get_tile(f, &il, &ql);
+    const int fam = sbf_get_variant(f);
+    sbf_destroy(f);
+    if (rc) break;
+    const double rate = valid ? (double)present / (double)valid : 0.0;
+    appendf(rep, "shard %2u words (%s kernels): insert %.4f ms (%u k-mers/lane), query %.4f ms (%u k-mers/lane), "
+                 "FPR %.4g (%llu of %llu negative k-mers)\n",
+            S, fam == SBF_VARIANT_ROLLING ? "lane" : fam == SBF_VARIANT_WIDE ? "wide-shard" : "generic", ti, il, tq,
+            ql, rate, (unsigned long long)present, (unsigned long long)valid);
+    const std::string indented = "    " + sub.substr(0, sub.size() ? sub.size() - 1 : 0);
+    std::string body;
+    for (char c : indented) {
+      body += c;
+      if (c == '\n') body += "    ";
+    }
+    rep += body + "\n";
+    const double ms = (double)ti + (double)tq;
+    if (rate < best_any.fpr || (rate == best_any.fpr && ms < best_any.ms)) best_any = {S, il, ql, rate, ms};
+    if (rate <= max_fpr && ms < best_ok.ms) best_ok = {S, il, ql, rate, ms};
+  }
+  if (!rc && best_any.S == 0) rc = set_error(SBF_E_INVAL, "no shard geometry exists for H=%u", H);
+  if (!rc) {
+    const Choice &c = best_ok.S ? best_ok : best_any;
+    appendf(rep, "%s: %u-word shards, %u/%u k-mers per lane, FPR %.4g, insert + query %.4f ms\n",
+            best_ok.S ? "fastest within the FPR bound" : "no geometry meets the FPR bound; lowest FPR", c.S, c.il,
+            c.ql, c.fpr, c.ms);
+    *shard_words = c.S;
+    if (insert_kmers_per_lane) *insert_kmers_per_lane = c.il;
+    if (query_kmers_per_lane) *query_kmers_per_lane = c.ql;
+    if (fpr) *fpr = c.fpr;
+  }
+  copy_report(rep, report, report_len);
+  if (rc) return rc;
   return ok();
 }
 

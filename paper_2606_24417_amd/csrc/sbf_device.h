@@ -164,4 +164,30 @@ __device__ __forceinline__ void atomic_or64(uint64_t *p, uint64_t v) {
   __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Filter accesses of the two-pass insert.  The store pass's read-OR-writes
+// of one shard race between workgroups on different XCDs, each with its own
+// write-back L2.  Measured on the MI355X: with plain stores the racing dirty
+// lines can reach memory after the repair walk's atomic ORs and overwrite
+// them (bits went missing in filters that fit the caches), while stores that
+// write through to the device's coherence point leave every word with one
+// order of values, each a superset of the word at launch, which the repair
+// walk then completes.  So the store pass writes each 16-byte half of its
+// shard update with a system-coherent store (a volatile global access:
+// global_store_dwordx4 with sc0 sc1), and the repair walk, whose reads race
+// with its own atomic ORs, reads words with agent-scope atomic loads.
+typedef __attribute__((address_space(1))) volatile u32x4 coherent_u32x4;
+
+__device__ __forceinline__ void store_pair_coherent(uint64_t *p, uint64_t a, uint64_t b) {
+  u32x4 v;
+  v[0] = (uint32_t)a;
+  v[1] = (uint32_t)(a >> 32);
+  v[2] = (uint32_t)b;
+  v[3] = (uint32_t)(b >> 32);
+  *(coherent_u32x4 *)p = v;
+}
+
+__device__ __forceinline__ uint64_t load_word(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace sbf

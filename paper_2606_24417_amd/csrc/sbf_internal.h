@@ -52,12 +52,23 @@ inline bool query_packed_supported(int mode) { return mode == kQueryLaneMode; }
 struct LaunchShape {
   uint32_t *queue;
   uint32_t persistent_wgs;
+  // k-mers per lane of the insert and query tiles (0: the kernel family's
+  // default; the compiled lengths are listed by lane_len_supported)
+  uint32_t insert_lane_len = 0;
+  uint32_t query_lane_len = 0;
 };
 
 hipError_t launch_insert_rolling(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode,
                                  const LaunchShape &ls, hipStream_t st);
 hipError_t launch_query_rolling(const Geometry &g, const uint64_t *words, const SeqArgs &a, int mode,
                                 const LaunchShape &ls, hipStream_t st);
+// Wide-shard kernels (kernels_wide.hip): shards of 4, 8 or 16 words for a
+// few compiled parameter sets; query answers as bytes only.
+bool wide_supported(const Geometry &g);
+hipError_t launch_insert_wide(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode, const LaunchShape &ls,
+                              hipStream_t st);
+hipError_t launch_query_wide(const Geometry &g, const uint64_t *words, const SeqArgs &a, const LaunchShape &ls,
+                             hipStream_t st);
 hipError_t launch_insert_generic(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st);
 hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);
 
@@ -75,6 +86,12 @@ void release_stream(sbf_filter *f, hipStream_t stream);
 // Utility kernels.
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t value, hipStream_t st);
+// Add the number of nonzero bytes of p[0, n) to the device counter *count.
+hipError_t launch_count_nonzero_u8(const uint8_t *p, uint64_t n, uint64_t *count, hipStream_t st);
+// Add to *sum, over shards, the probability that a k-mer of ideal hashes
+// sent to the shard finds all its bits set, and to *bits the set bits.
+hipError_t launch_estimate_fpr(const Geometry &g, const uint64_t *words, double *sum, uint64_t *bits,
+                               hipStream_t st);
 // Set bit off[r] of `starts` for r = 1 .. nrec-1 (starts must be zeroed;
 // ceil(len/32) words).
 hipError_t launch_mark_record_starts(const uint64_t *off, uint64_t nrec, uint64_t len, uint32_t *starts,

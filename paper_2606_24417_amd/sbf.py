@@ -24,6 +24,7 @@ SBF_E_BUSY = -4
 VARIANT_AUTO = 0
 VARIANT_ROLLING = 1
 VARIANT_GENERIC = 2
+VARIANT_WIDE = 3
 INSERT_TWO_PASS = 0
 INSERT_ATOMIC = 1
 QUERY_LANE = 0
@@ -49,6 +50,7 @@ SIGNATURES = {
     "sbf_set_bits": (_int, [_vp, _vp, _u64]),
     "sbf_clear": (_int, [_vp, _vp]),
     "sbf_device_words": (_vp, [_vp]),
+    "sbf_estimate_fpr": (_int, [_vp, _vp, _vp]),
     "sbf_insert_seq_dev": (_int, [_vp, _vp, _u64, _vp]),
     "sbf_query_seq_dev": (_int, [_vp, _vp, _u64, _vp, _vp]),
     "sbf_insert_batch": (_int, [_vp, _vp, _vp, _u64]),
@@ -70,6 +72,10 @@ SIGNATURES = {
     "sbf_graph_launch": (_int, [_vp, _vp]),
     "sbf_graph_destroy": (None, [_vp]),
     "sbf_autotune": (_int, [_vp, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64]),
+    "sbf_autotune_geometry": (_int, [_u32, _u32, _u32, _u32, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _vp,
+                                     _u64, _vp, _u64, ctypes.c_double, _vp, _vp, _vp, _vp, _vp, _u64]),
+    "sbf_set_tile": (_int, [_vp, _u32, _u32]),
+    "sbf_get_tile": (_int, [_vp, _vp, _vp]),
     "sbf_server_create": (_vp, [_vp, _u32, _u64, _u64, _u32]),
     "sbf_server_set_batch_window": (_int, [_vp, _u64]),
     "sbf_server_submit": (_int, [_vp, _vp, _vp, _u64, _vp, _vp]),
@@ -213,6 +219,15 @@ class Filter:
         return {"insert_wgs_per_cu": iw.value, "query_wgs_per_cu": qw.value, "insert_mode": im.value,
                 "query_mode": qm.value}
 
+    def set_tile(self, insert_kmers_per_lane: int = 0, query_kmers_per_lane: int = 0):
+        """k-mers per lane of the insert and query tiles (0 = default)."""
+        _check(lib().sbf_set_tile(self._h, int(insert_kmers_per_lane), int(query_kmers_per_lane)))
+
+    def get_tile(self) -> tuple:
+        i, q = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().sbf_get_tile(self._h, ctypes.byref(i), ctypes.byref(q)))
+        return i.value, q.value
+
     def autotune(self, ins, ins_off, q, q_off) -> str:
         """Time launch shapes and kernel organisations on device batches and keep
         the fastest (sbf_autotune).  Returns the timing report."""
@@ -234,6 +249,13 @@ class Filter:
     def set_bits(self, words):
         a = np.ascontiguousarray(words, dtype=np.uint64)
         _check(lib().sbf_set_bits(self._h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+
+    def estimate_fpr(self):
+        """(expected FPR of absent uniformly sharded k-mers, set bits) from the
+        filter's sector popcounts (sbf_estimate_fpr)."""
+        fpr, nb = ctypes.c_double(), ctypes.c_uint64()
+        _check(lib().sbf_estimate_fpr(self._h, ctypes.byref(fpr), ctypes.byref(nb)))
+        return fpr.value, nb.value
 
     def clear(self, stream=None):
         _check(lib().sbf_clear(self._h, _stream_handle(stream)))
@@ -339,6 +361,25 @@ class Filter:
                                                  ctypes.c_void_p(offsets.data_ptr()), offsets.numel() - 1,
                                                  ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
         return out
+
+
+def autotune_geometry(k, s, m, H, bits, ins, ins_off, q, q_off, neg, neg_off, max_fpr):
+    """Shard-geometry autotuner (sbf_autotune_geometry) on device batches:
+    returns a dict with the chosen shard words, tile lengths, FPR and the
+    report of every trial."""
+    def p(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    S, il, ql = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    fpr = ctypes.c_double()
+    buf = ctypes.create_string_buffer(65536)
+    _check(lib().sbf_autotune_geometry(int(k), int(s), int(m), int(H), int(bits), p(ins), ins.numel(), p(ins_off),
+                                       ins_off.numel() - 1, p(q), q.numel(), p(q_off), q_off.numel() - 1, p(neg),
+                                       neg.numel(), p(neg_off), neg_off.numel() - 1, float(max_fpr),
+                                       ctypes.byref(S), ctypes.byref(il), ctypes.byref(ql), ctypes.byref(fpr), buf,
+                                       len(buf)))
+    return {"shard_words": S.value, "insert_kmers_per_lane": il.value, "query_kmers_per_lane": ql.value,
+            "fpr": fpr.value, "report": buf.value.decode()}
 
 
 class Graph:

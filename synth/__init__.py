@@ -274,3 +274,19 @@ def batched_workload(scale: float = 1.0):
     kmers = int(np.maximum(np.diff(ins[1].astype(np.int64)) - 30, 0).sum())
     return dict(name="batched: 2M log-normal reads (median 500 bp) inserted, 2M queried", k=31, s=28, m=16, H=4,
                 bits=16 * kmers, insert=ins, query=q)
+
+
+def separated_uniform_kmers(n: int, k: int, seed: int, device="cpu"):
+    """n independent uniform k-mers as one record of n*(k+1) bases on a torch
+    device: each k-mer is followed by one 'N', so the record's valid k-mers
+    are exactly the n drawn ones, at positions i*(k+1).  Drawn with torch's
+    seeded generator on that device (the stream differs between devices)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    c = torch.randint(0, 4, (n, k + 1), generator=g, device=device, dtype=torch.uint8)
+    # codes 0..3 -> 'A' 'C' 'G' 'T' (65, 67, 71, 84) without a gather
+    seq = 65 + 2 * c + 2 * (c >= 2).to(torch.uint8) + 11 * (c == 3).to(torch.uint8)
+    seq[:, k] = ord("N")
+    return seq.reshape(-1)

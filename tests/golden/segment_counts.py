@@ -14,8 +14,9 @@
   GPU's filter and answers with these digests, and bench.py compares its
   answer count with the stored one.
 
-    python tests/golden/segment_counts.py [workload ...]
-        (default: tiny in_cache out_of_cache batched)
+    python tests/golden/segment_counts.py [--shard-words S] [workload ...]
+        (default: tiny in_cache out_of_cache batched; S = 4, the paper's
+        shard; with S = 8 or 16 the entries are stored as <workload>_S<S>)
 
 Calls only oracle/ and synth/; the oracle runs on every CPU (threads over
 k-1-overlapping pieces, atomic ORs into one filter).
@@ -84,14 +85,16 @@ def count(p, batch, parts: int = 64) -> int:
         return int(sum(ex.map(lambda j: oracle.count_segments(p, j[0], j[1]), jobs)))
 
 
-def main(names):
+def main(names, shard_words=4):
     res = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         t0 = time.perf_counter()
         w = WORKLOADS[name]()
-        p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"])
+        p = oracle.Params(w["k"], w["s"], w["m"], w["H"], w["bits"], shard_words=shard_words)
         entry = {"workload": w["name"], "k": w["k"], "s": w["s"], "m": w["m"], "H": w["H"],
                  "filter_bits_requested": int(w["bits"]), "nshards": int(p.nshards)}
+        if shard_words != 4:
+            entry["shard_words"] = shard_words
         for part in ("insert", "query"):
             seq, off = w[part]
             entry[part] = {"bases": int(seq.size), "kmers": kmer_positions(off, w["k"]),
@@ -109,7 +112,7 @@ def main(names):
         entry["oracle_answers"] = {"bytes": int(ans.size), "present": int(ans.sum(dtype=np.int64)),
                                    "sha256": whole, "block_bytes": ANSWER_BLOCK_BYTES, "block_sha256": blocks}
         del ans
-        res[name] = entry
+        res[name if shard_words == 4 else "%s_S%d" % (name, shard_words)] = entry
         print(name, json.dumps({k: v for k, v in entry.items() if not k.startswith("oracle")}),
               "present", entry["oracle_answers"]["present"], "%.0fs" % (time.perf_counter() - t0), flush=True)
         del w
@@ -119,4 +122,9 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["tiny", "in_cache", "out_of_cache", "batched"])
+    argv = sys.argv[1:]
+    sw = 4
+    if argv[:1] == ["--shard-words"]:
+        sw = int(argv[1])
+        argv = argv[2:]
+    main(argv or ["tiny", "in_cache", "out_of_cache", "batched"], sw)
