@@ -138,6 +138,7 @@ __global__ __launch_bounds__(kGenericWG) void query_generic_kernel(const uint8_t
                                                                    int aligned16,
                                                                    const uint64_t *__restrict__ words, RtParams p,
                                                                    uint8_t *__restrict__ out, uint64_t n_out) {
+  acquire_device();  // no filter line cached before this launch is read
   __shared__ uint32_t s_codes[kGenericGran];
   __shared__ uint32_t s_vb[kGenericGran];
   const uint64_t base = (uint64_t)blockIdx.x * kGenericTile;

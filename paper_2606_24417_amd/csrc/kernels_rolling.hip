@@ -162,6 +162,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
   __shared__ SegmentBuffer<(MODE == kAtomic ? 1 : WG)> s_buf;
 
   __shared__ uint32_t s_next_tile;
+  acquire_device();
   uint64_t tile;
   for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
   const uint64_t base = (uint64_t)tile * (uint64_t)(WG * L);
@@ -327,6 +328,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
   __shared__ uint32_t s_kv[WG];
 
   __shared__ uint32_t s_next_tile;
+  acquire_device();
   uint64_t tile;
   for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
   const uint64_t base = (uint64_t)tile * (uint64_t)TILE;
@@ -484,6 +486,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
   __shared__ uint64_t s_vh[W][WG];
 
   __shared__ uint32_t s_next_tile;
+  acquire_device();
   uint64_t tile;
   for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
   const uint64_t base = (uint64_t)tile * (uint64_t)(WG * L);
@@ -592,18 +595,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
             const bool fresh = r == 0 || sh != prev_sh;
             prev_sh = sh;
             const uint32_t lsh = fresh ? sh : 0u;
-            if constexpr (REPAIR) {
-              // the repair's reads race with its own atomic ORs: atomic loads
-#pragma unroll
-              for (int w = 0; w < 4; ++w) ldw[r][w] = load_word(words + 4ull * (uint64_t)lsh + w);
-            } else {
-              const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)lsh);
-              const uint4 lo = p[0], hi = p[1];
-              ldw[r][0] = ((uint64_t)lo.y << 32) | lo.x;
-              ldw[r][1] = ((uint64_t)lo.w << 32) | lo.z;
-              ldw[r][2] = ((uint64_t)hi.y << 32) | hi.x;
-              ldw[r][3] = ((uint64_t)hi.w << 32) | hi.z;
-            }
+            const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)lsh);
+            const uint4 lo = p[0], hi = p[1];
+            ldw[r][0] = ((uint64_t)lo.y << 32) | lo.x;
+            ldw[r][1] = ((uint64_t)lo.w << 32) | lo.z;
+            ldw[r][2] = ((uint64_t)hi.y << 32) | hi.x;
+            ldw[r][3] = ((uint64_t)hi.w << 32) | hi.z;
             fresh_at[r] = fresh;
             sh_at[r] = sh;
             smer_onehots<H>(smer_hash(smer_at<S>(a, r + Z)), oh[r + Z]);

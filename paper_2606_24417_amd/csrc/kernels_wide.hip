@@ -191,6 +191,7 @@ __global__ __launch_bounds__(WG) void insert_wide_kernel(const uint8_t *__restri
   const int e = (2 * p) & 3;                // sector of word 2p (0 or 2)
   const uint32_t grp = (uint32_t)(p >> 1);  // word group of words 2p, 2p+1
 
+  acquire_device();
   uint64_t tile;
   for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
     const uint64_t base = tile * (uint64_t)Tl::TILE;
@@ -299,6 +300,7 @@ __global__ __launch_bounds__(WG) void query_wide_kernel(const uint8_t *__restric
   const int d0 = (e * HALF + 2 * grp) / 2;  // dword pair index of word 2p
   const int d1 = ((e + 1) * HALF + 2 * grp) / 2;
 
+  acquire_device();
   uint64_t tile;
   for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
     const uint64_t base = tile * (uint64_t)Tl::TILE;
@@ -323,16 +325,9 @@ __global__ __launch_bounds__(WG) void query_wide_kernel(const uint8_t *__restric
           if (slot < PASS && j < nruns) {
             const uint32_t rsh = s_run_shard[wave][j];
             const uint64_t *src = words + (uint64_t)rsh * SW + 2 * p;
-            uint64_t w0, w1;
-            if constexpr (REPAIR) {
-              // the repair's reads race with its own atomic ORs: atomic loads
-              w0 = load_word(src);
-              w1 = load_word(src + 1);
-            } else {
-              const uint4 piece = *reinterpret_cast<const uint4 *>(src);
-              w0 = ((uint64_t)piece.y << 32) | piece.x;
-              w1 = ((uint64_t)piece.w << 32) | piece.z;
-            }
+            const uint4 piece = *reinterpret_cast<const uint4 *>(src);
+            const uint64_t w0 = ((uint64_t)piece.y << 32) | piece.x;
+            const uint64_t w1 = ((uint64_t)piece.w << 32) | piece.z;
             s_line[wave][slot][d0] = make_uint2((uint32_t)w0, (uint32_t)(w0 >> 32));
             s_line[wave][slot][d1] = make_uint2((uint32_t)w1, (uint32_t)(w1 >> 32));
           }

@@ -169,12 +169,11 @@ __device__ __forceinline__ void atomic_or64(uint64_t *p, uint64_t v) {
 // write-back L2.  Measured on the MI355X: with plain stores the racing dirty
 // lines can reach memory after the repair walk's atomic ORs and overwrite
 // them (bits went missing in filters that fit the caches), while stores that
-// write through to the device's coherence point leave every word with one
-// order of values, each a superset of the word at launch, which the repair
-// walk then completes.  So the store pass writes each 16-byte half of its
-// shard update with a system-coherent store (a volatile global access:
-// global_store_dwordx4 with sc0 sc1), and the repair walk, whose reads race
-// with its own atomic ORs, reads words with agent-scope atomic loads.
+// write through to the coherence point leave every word with one order of
+// values, each a superset of the word at launch, which the repair walk then
+// completes with agent-scope atomic ORs.  So the store pass writes each
+// 16-byte half of its shard update with a system-coherent store (a volatile
+// global access: global_store_dwordx4 with sc0 sc1).
 typedef __attribute__((address_space(1))) volatile u32x4 coherent_u32x4;
 
 __device__ __forceinline__ void store_pair_coherent(uint64_t *p, uint64_t a, uint64_t b) {
@@ -186,8 +185,13 @@ __device__ __forceinline__ void store_pair_coherent(uint64_t *p, uint64_t a, uin
   *(coherent_u32x4 *)p = v;
 }
 
-__device__ __forceinline__ uint64_t load_word(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Every workgroup of the insert, repair and query kernels starts with an
+// agent-scope acquire (buffer_inv sc1: its XCD's L2 drops its lines), so
+// that no load of the launch returns a copy cached before it.  Within a
+// launch a plain load may then only miss bits that other workgroups are
+// adding at the same time: the store pass loses them to a racing update and
+// the repair walk restores them, and the repair walk, whose plain loads race
+// only with its own atomic ORs, at worst repeats an OR.
+__device__ __forceinline__ void acquire_device() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 }  // namespace sbf
