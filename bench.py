@@ -254,7 +254,8 @@ def stored_segments(workload_name: str, part: str, kmers: int):
     return int(d["segments"])
 
 
-PROBE_NAMES = ["read", "rmw", "atomic4", "atomic1", "copy", "read_line", "rmw_line"]
+PROBE_NAMES = ["read", "rmw", "atomic4", "atomic1", "copy", "read_line", "rmw_line", "rmw_coherent",
+               "rmw_line_coherent"]
 # in-flight depths compiled into the probe per shard size (include/sbf_probe.h)
 PROBE_DEPTHS = {32: (1, 4, 8, 16), 64: (1, 4, 8), 128: (1, 2, 4)}
 PROBE_WGS = (1, 2, 4, 8)
@@ -850,6 +851,7 @@ def main():
         run_probes([2, 32, 256, 1024, 8192])
         run_probes([8192], modes=(0, 1), shard_bytes=(64, 128))
         run_probes([8192], modes=(5, 6), shard_bytes=(32, 64, 128))
+        run_probes([256, 8192], modes=(7, 8), shard_bytes=(32, 128))
         for mib in (2, 32, 256, 8192):
             run_copy_probe(mib)
         run_valu_probes()

@@ -27,6 +27,8 @@ extern "C" {
 #define SBF_PROBE_COPY 4     /* streaming copy of bytes/2 bytes within the buffer */
 #define SBF_PROBE_READ_LINE 5 /* as READ, the shard split over shard_bytes/16 lanes (one 16-byte piece each) */
 #define SBF_PROBE_RMW_LINE 6  /* as RMW, the shard split over shard_bytes/16 lanes */
+#define SBF_PROBE_RMW_COHERENT 7      /* as RMW, the stores writing through to the coherence point (sc0 sc1) */
+#define SBF_PROBE_RMW_LINE_COHERENT 8 /* as RMW_LINE with those stores */
 
 /* Run probe `mode` over a device buffer of `bytes` bytes (a power of two,
  * 64 KiB .. 64 GiB; allocated, zeroed and freed by the call) on the current

@@ -97,22 +97,34 @@ __device__ __forceinline__ void push_segment(SegmentBuffer<WG> &b, int &n, uint6
 template <int MODE, int WG>
 __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uint64_t *__restrict__ words) {
   if constexpr (MODE != kAtomic) {
+    // The lanes of each aligned pair read (and below write) both 16-byte
+    // halves of one shard in one instruction: load A takes the even lane's
+    // shard (low half by the even lane, high half by the odd lane), load B
+    // the odd lane's; afterwards each lane swaps the half it read for its
+    // partner.  A shard moved by two lanes of one instruction is one 32-byte
+    // access instead of two 16-byte ones.
     const int t = threadIdx.x;
+    const bool odd = (threadIdx.x & 1) != 0;
     uint32_t sh[kQueueSlots];
     uint64_t m[kQueueSlots][4], old[kQueueSlots][4];
+    uint4 la[kQueueSlots], lb[kQueueSlots];
+    bool own[kQueueSlots], p_own[kQueueSlots];
 #pragma unroll
     for (int k = 0; k < kQueueSlots; ++k) {
-      if (k < n) {
-        sh[k] = b.shard[k][t];
+      own[k] = k < n;
+      sh[k] = own[k] ? b.shard[k][t] : 0u;
+      if (own[k]) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) m[k][w] = b.mask[k][w][t];
-        const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)sh[k]);
-        const uint4 lo = p[0], hi = p[1];
-        old[k][0] = ((uint64_t)lo.y << 32) | lo.x;
-        old[k][1] = ((uint64_t)lo.w << 32) | lo.z;
-        old[k][2] = ((uint64_t)hi.y << 32) | hi.x;
-        old[k][3] = ((uint64_t)hi.w << 32) | hi.z;
       }
+      p_own[k] = pair_swap((uint32_t)own[k]) != 0u;
+      const uint32_t ps = pair_swap(sh[k]);
+      la[k] = make_uint4(0, 0, 0, 0);
+      lb[k] = make_uint4(0, 0, 0, 0);
+      if (odd ? p_own[k] : own[k])
+        la[k] = *reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)(odd ? ps : sh[k]) + (odd ? 2 : 0));
+      if (odd ? own[k] : p_own[k])
+        lb[k] = *reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)(odd ? sh[k] : ps) + (odd ? 2 : 0));
     }
     // Wait for the loads here, on every path: the stores below are
     // conditional, and a load the compiler still counts as outstanding after
@@ -120,6 +132,19 @@ __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uin
     // (the vector-memory counter retires in order).  s_waitcnt vmcnt(0), the
     // other counters left at their maxima.
     __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+    for (int k = 0; k < kQueueSlots; ++k) {
+      // the even lane keeps A (its low half) and receives its high half from
+      // the odd lane's A; the odd lane keeps B (its high half) and receives
+      // its low half from the even lane's B
+      const uint4 x = odd ? la[k] : lb[k];
+      const uint4 px = make_uint4(pair_swap(x.x), pair_swap(x.y), pair_swap(x.z), pair_swap(x.w));
+      const uint4 lo = odd ? px : la[k], hi = odd ? lb[k] : px;
+      old[k][0] = ((uint64_t)lo.y << 32) | lo.x;
+      old[k][1] = ((uint64_t)lo.w << 32) | lo.z;
+      old[k][2] = ((uint64_t)hi.y << 32) | hi.x;
+      old[k][3] = ((uint64_t)hi.w << 32) | hi.z;
+    }
     // a later buffered segment on the same shard carries the earlier masks,
     // since its read does not see the earlier write of this lane
 #pragma unroll
@@ -129,14 +154,30 @@ __device__ __forceinline__ void drain_segments(SegmentBuffer<WG> &b, int &n, uin
         if (k < n && sh[k] == sh[j])
 #pragma unroll
           for (int w = 0; w < 4; ++w) m[k][w] |= m[j][w];
+    // Stores that write through to the coherence point (store_pair_coherent)
+    // cost two partial writes when one lane writes a 32-byte shard as two
+    // 16-byte halves, but one when two lanes write its halves in the same
+    // instruction.  So the lanes of each aligned pair write each other's
+    // shard halves: in store A the pair writes the even lane's shard (low half
+    // from the even lane, high half from the odd lane), in store B the odd
+    // lane's shard.  A given half of a shard is always written by the same
+    // lane of the pair, so a lane's stores to one shard stay in order.
 #pragma unroll
     for (int k = 0; k < kQueueSlots; ++k) {
-      if (k < n) {
-        // coherent stores: see store_pair_coherent
-        uint64_t *p = words + 4ull * (uint64_t)sh[k];
-        store_pair_coherent(p, old[k][0] | m[k][0], old[k][1] | m[k][1]);
-        store_pair_coherent(p + 2, old[k][2] | m[k][2], old[k][3] | m[k][3]);
-      }
+      uint64_t v[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) v[w] = own[k] ? (old[k][w] | m[k][w]) : 0ull;
+      const uint32_t s = sh[k];
+      const uint32_t ps = pair_swap(s);
+      // the half the other lane writes: the even lane's high, the odd lane's low
+      const uint64_t px0 = pair_swap64(odd ? v[0] : v[2]);
+      const uint64_t px1 = pair_swap64(odd ? v[1] : v[3]);
+      if (odd ? p_own[k] : own[k])
+        store_pair_coherent(words + 4ull * (uint64_t)(odd ? ps : s) + (odd ? 2 : 0), odd ? px0 : v[0],
+                            odd ? px1 : v[1]);
+      if (odd ? own[k] : p_own[k])
+        store_pair_coherent(words + 4ull * (uint64_t)(odd ? s : ps) + (odd ? 2 : 0), odd ? v[2] : px0,
+                            odd ? v[3] : px1);
     }
     n = 0;
   }
@@ -185,7 +226,9 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
     uint32_t fsh = 0;
     bool held = false;
     int nbuf = 0;
-    if (kv != 0) {
+    // every lane walks, also one without valid k-mers (it opens no segment):
+    // the drains exchange data between lanes
+    {
       // one-hot masks of s-mers r .. r+Z, OR-ed: A(r).  For Z = 3 the window OR
       // reuses pairs P(j) = oh(j) | oh(j+1): A(r) = P(r) | P(r+2).
       uint64_t oh[L + Z][4];

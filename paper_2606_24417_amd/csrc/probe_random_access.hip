@@ -34,6 +34,20 @@ __device__ __forceinline__ uint64_t scramble(uint64_t x) {
 // each shard: lane c of the group loads and stores 16-byte piece c, so one
 // wave instruction covers 64 * 16 / SB whole shards (the access pattern of
 // the wide-shard kernels, which move a super-k-mer's line with SB/16 lanes).
+// Store of a 16-byte chunk that writes through to the device's coherence
+// point (a volatile global access: global_store_dwordx4 with sc0 sc1), the
+// store the filter's insert kernels use for their racing read-modify-writes.
+typedef uint32_t probe_u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) volatile probe_u32x4 probe_coherent_u32x4;
+__device__ __forceinline__ void store_coherent(uint4 *q, const uint4 &v) {
+  probe_u32x4 x;
+  x[0] = v.x;
+  x[1] = v.y;
+  x[2] = v.z;
+  x[3] = v.w;
+  *(probe_coherent_u32x4 *)q = x;
+}
+
 template <int MODE, int SB, int D, bool COOP = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void random_shards(uint64_t *__restrict__ buf, uint64_t shard_mask,
                                                         uint64_t seed, uint32_t batches,
@@ -56,7 +70,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       bit[d] = 1ull << (h >> 58);
     }
     if constexpr (MODE == SBF_PROBE_READ || MODE == SBF_PROBE_RMW || MODE == SBF_PROBE_READ_LINE ||
-                  MODE == SBF_PROBE_RMW_LINE) {
+                  MODE == SBF_PROBE_RMW_LINE || MODE == SBF_PROBE_RMW_COHERENT || MODE == SBF_PROBE_RMW_LINE_COHERENT) {
       uint4 v[D][C];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
@@ -85,7 +99,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
           v[d][C - 1].w |= (uint32_t)(bit[d] >> 32);
           uint4 *q = reinterpret_cast<uint4 *>(buf + idx[d] * (SB / 8)) + piece;
 #pragma unroll
-          for (int c = 0; c < C; ++c) q[c] = v[d][c];
+          for (int c = 0; c < C; ++c) {
+            if constexpr (MODE == SBF_PROBE_RMW_COHERENT || MODE == SBF_PROBE_RMW_LINE_COHERENT)
+              store_coherent(q + c, v[d][c]);
+            else
+              q[c] = v[d][c];
+          }
         }
       }
     } else {
@@ -125,7 +144,8 @@ template <int MODE>
 hipError_t launch_random(uint64_t *buf, uint64_t bytes, uint32_t sb, uint32_t d, unsigned grid, uint32_t batches,
                          uint64_t seed, uint64_t *sink) {
   const uint64_t mask = bytes / sb - 1;
-  constexpr bool coop = MODE == SBF_PROBE_READ_LINE || MODE == SBF_PROBE_RMW_LINE;
+  constexpr bool coop =
+      MODE == SBF_PROBE_READ_LINE || MODE == SBF_PROBE_RMW_LINE || MODE == SBF_PROBE_RMW_LINE_COHERENT;
 #define SBF_PROBE_CASE(SB_, D_)                                                                              \
   if (sb == SB_ && d == D_) {                                                                                \
     hipLaunchKernelGGL((random_shards<MODE, SB_, D_, coop>), dim3(grid), dim3(kBlock), 0, 0, buf, mask, seed,    \
@@ -153,6 +173,10 @@ hipError_t launch(int mode, uint64_t *buf, uint64_t bytes, uint32_t sb, uint32_t
     case SBF_PROBE_ATOMIC4: return launch_random<SBF_PROBE_ATOMIC4>(buf, bytes, sb, d, grid, batches, seed, sink);
     case SBF_PROBE_READ_LINE: return launch_random<SBF_PROBE_READ_LINE>(buf, bytes, sb, d, grid, batches, seed, sink);
     case SBF_PROBE_RMW_LINE: return launch_random<SBF_PROBE_RMW_LINE>(buf, bytes, sb, d, grid, batches, seed, sink);
+    case SBF_PROBE_RMW_COHERENT:
+      return launch_random<SBF_PROBE_RMW_COHERENT>(buf, bytes, sb, d, grid, batches, seed, sink);
+    case SBF_PROBE_RMW_LINE_COHERENT:
+      return launch_random<SBF_PROBE_RMW_LINE_COHERENT>(buf, bytes, sb, d, grid, batches, seed, sink);
     default: return launch_random<SBF_PROBE_ATOMIC1>(buf, bytes, sb, d, grid, batches, seed, sink);
   }
 }
@@ -244,7 +268,7 @@ extern "C" int sbf_probe_valu(int op, double *wave_instr_per_second, double *ms)
 
 extern "C" int sbf_probe_random_access(uint64_t bytes, int mode, uint32_t shard_bytes, uint32_t inflight,
                                        uint32_t wgs_per_cu, uint64_t ops, double *per_second, double *ms) {
-  if (!per_second || !ms || mode < SBF_PROBE_READ || mode > SBF_PROBE_RMW_LINE) return -1;
+  if (!per_second || !ms || mode < SBF_PROBE_READ || mode > SBF_PROBE_RMW_LINE_COHERENT) return -1;
   if (bytes < (1ull << 16) || bytes > (1ull << 36) || (bytes & (bytes - 1))) return -1;
   if (mode != SBF_PROBE_COPY && (!depth_supported(shard_bytes, inflight) || wgs_per_cu < 1 || wgs_per_cu > 16))
     return -1;
@@ -255,7 +279,9 @@ extern "C" int sbf_probe_random_access(uint64_t bytes, int mode, uint32_t shard_
   const unsigned grid = (unsigned)cus * wgs_per_cu;
   // shard operations per batch of the grid (a shard per SB/16 lanes in the _LINE modes)
   const uint64_t lanes_per_shard =
-      (mode == SBF_PROBE_READ_LINE || mode == SBF_PROBE_RMW_LINE) ? (uint64_t)shard_bytes / 16 : 1;
+      (mode == SBF_PROBE_READ_LINE || mode == SBF_PROBE_RMW_LINE || mode == SBF_PROBE_RMW_LINE_COHERENT)
+          ? (uint64_t)shard_bytes / 16
+          : 1;
   const uint64_t per_batch = (uint64_t)grid * kBlock * (mode == SBF_PROBE_COPY ? 1 : inflight) / lanes_per_shard;
   if (ops < (1ull << 20)) ops = 1ull << 20;
   const uint64_t nb = (ops + per_batch - 1) / per_batch;

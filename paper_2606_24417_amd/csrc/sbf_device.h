@@ -185,6 +185,15 @@ __device__ __forceinline__ void store_pair_coherent(uint64_t *p, uint64_t a, uin
   *(coherent_u32x4 *)p = v;
 }
 
+// Value of the other lane of an aligned lane pair (lane ^ 1), by a DPP quad
+// permutation [1, 0, 3, 2]; every lane of the wave must be active.
+__device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint64_t pair_swap64(uint64_t x) {
+  return ((uint64_t)pair_swap((uint32_t)(x >> 32)) << 32) | pair_swap((uint32_t)x);
+}
+
 // Every workgroup of the insert, repair and query kernels starts with an
 // agent-scope acquire (buffer_inv sc1: its XCD's L2 drops its lines), so
 // that no load of the launch returns a copy cached before it.  Within a
