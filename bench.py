@@ -36,7 +36,8 @@ PEAK_INT_TOPS = 39.3216      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, 32-bit inte
 # s-mer hash 10, H=4 bit addresses 4; insert adds one-hot + segment OR 16,
 # query adds the (k-s+1)*H = 16 bit tests at 2 ops each plus the output 1)
 OPS_PER_KMER = {"insert": 46, "query": 63}
-KERNEL_SOURCES = ["paper_2606_24417_amd/csrc/kernels_rolling.hip", "paper_2606_24417_amd/csrc/sbf_device.h"]
+KERNEL_SOURCES = ["paper_2606_24417_amd/csrc/kernels_rolling.hip", "paper_2606_24417_amd/csrc/kernels_wide.hip",
+                  "paper_2606_24417_amd/csrc/sbf_tiles.h", "paper_2606_24417_amd/csrc/sbf_device.h"]
 
 
 def kernel_source_hash() -> str:
@@ -1033,13 +1034,15 @@ def measure(args, name, with_cpu):
         # size over an 8 GiB buffer (best over in-flight depth and occupancy,
         # with the shard moved by one lane or split over shard/16 lanes as the
         # wide-shard kernels do), measured now
+        # (the insert's read-modify-writes race between XCDs, so its stores
+        # write through to the coherence point; the probe does the same)
         probe = {}
         sb = 8 * S
-        for mode, line_mode in ((0, 5), (1, 6)):
+        for key, mode, line_mode in (("read", 0, 5), ("rmw", 7, 8)):
             best, _ = probe_ceiling(8192, mode, sb)
             best_l, _ = probe_ceiling(8192, line_mode, sb)
             best_l["lanes_per_shard"] = sb // 16
-            probe[PROBE_NAMES[mode]] = best if best["G_per_s"] >= best_l["G_per_s"] else best_l
+            probe[key] = best if best["G_per_s"] >= best_l["G_per_s"] else best_l
         print("[bench] random-access ceilings (8 GiB, %d B): %s" % (sb, json.dumps(probe)), file=sys.stderr, flush=True)
 
     def roofline(part, ms, kmers, launches):
@@ -1061,7 +1064,7 @@ def measure(args, name, with_cpu):
                 r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "segments": nseg,
                      "algorithmic_bytes": nbytes}
-        r["traffic"] = counter_traffic(name, part, kmers)
+        r["traffic"] = counter_traffic(key, part, kmers)
         if in_cache and valu is not None:
             # the same algorithmic ops against the 32-bit add rate measured now
             # on this GPU (simple 32-bit ops issue faster than one wave64
@@ -1069,14 +1072,15 @@ def measure(args, name, with_cpu):
             # unit-count peak)
             r["valu_probe"] = {"add32_T_lane_ops_per_s": valu, "frac": round(r["achieved"] / valu, 4)}
         if probe is not None and r.get("segments"):
-            # segments (one random 32-byte shard access each) per second against
+            # segments (one random access of a whole shard each) per second against
             # the probe's best random read rate (query) or read-modify-write
             # rate (insert)
             seg_rate = r["segments"] / (ms * 1e-3)
             best = probe["read" if part == "query" else "rmw"]
             peak = best["G_per_s"] * 1e9
             r["random_access"] = {"segments_per_s": seg_rate, "probe_ceiling_per_s": peak,
-                                  "probe": ("read" if part == "query" else "read-modify-write") + " %d B" % (8 * S),
+                                  "probe": ("read" if part == "query" else "read-modify-write, coherent stores")
+                                  + " %d B" % (8 * S),
                                   "probe_setting": {"inflight": best["inflight"], "wgs_per_cu": best["wgs_per_cu"]},
                                   "frac": round(seg_rate / peak, 4)}
         r["launches"] = launches
