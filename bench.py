@@ -824,7 +824,7 @@ def main():
                     help="out_of_cache: skip the in-cache workload reported as a second key")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the live roofline probes (random access out of cache, 32-bit add rate in cache)")
-    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic, 3 wide-shard")
+    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 rolling, 2 generic, 3 wide-shard, 4 run-time parameter")
     ap.add_argument("--shard-words", type=int, default=4, choices=[4, 8, 16],
                     help="64-bit words per shard (4 = the paper's 256-bit shard)")
     ap.add_argument("--tile", type=str, default="", help="k-mers per lane for insert,query (0 = default)")
@@ -1009,7 +1009,7 @@ def measure(args, name, with_cpu):
     # Roofline of the dominant work: the insert is two launches (store pass,
     # then repair walk) unless it runs in atomic mode; the query is one.
     settings = f.get_launch()
-    family = {1: "lane", 2: "generic", 3: "wide-shard"}[f.variant]
+    family = {1: "lane", 2: "generic", 3: "wide-shard", 4: "run-time parameter"}[f.variant]
     tile_i, tile_q = f.get_tile()
     settings.update({"family": family, "shard_words": S, "insert_kmers_per_lane": tile_i,
                      "query_kmers_per_lane": tile_q})
@@ -1018,6 +1018,10 @@ def measure(args, name, with_cpu):
         q_kernel = "query_wide_kernel<31,28,16,4,%d,%d>" % (S, tile_q)
         ins_kernels = ("insert_wide_kernel<31,28,16,4,%d,%d> store pass + query_wide_kernel<31,28,16,4,%d,%d> repair "
                        "walk" % (S, tile_i, S, tile_i), "insert_wide_kernel<31,28,16,4,%d,%d> (atomic)" % (S, tile_i))
+    elif family == "run-time parameter":
+        q_kernel = "query_param_kernel<%d,%d>" % (S, tile_q)
+        ins_kernels = ("insert_param_kernel<%d,%d> store pass + query_param_kernel<%d,%d> repair walk"
+                       % (S, tile_i, S, tile_i), "insert_param_kernel<%d,%d> (atomic)" % (S, tile_i))
     else:
         q_kernel = {0: "query_lane_kernel", 1: "query_rolling_kernel (leader)", 2: "query_rolling_kernel (direct)"}[
             settings["query_mode"]] + "<31,28,16,4>"

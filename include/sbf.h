@@ -50,10 +50,12 @@ extern "C" {
 #define SBF_E_BUSY (-4)   /* a request was not admitted: the server's queue is full */
 
 /* Kernel families (sbf_set_variant). */
-#define SBF_VARIANT_AUTO 0    /* super-k-mer kernels when compiled for (k,s,m,H) and the shard size, else generic */
-#define SBF_VARIANT_ROLLING 1 /* super-k-mer kernels: lane kernels for 4-word shards, wide-shard kernels for 8/16 */
+#define SBF_VARIANT_AUTO 0    /* the fastest super-k-mer kernels for (k,s,m,H) and the shard size, else generic */
+#define SBF_VARIANT_ROLLING 1 /* super-k-mer kernels: lane kernels for 4-word shards, wide-shard kernels for 8/16,
+                                 run-time parameter kernels for other (k,s,m,H) */
 #define SBF_VARIANT_GENERIC 2 /* one k-mer per lane, run-time k, s, m, H */
 #define SBF_VARIANT_WIDE 3    /* wide-shard (two-phase, whole-line) super-k-mer kernels, also for 4-word shards */
+#define SBF_VARIANT_PARAM 4   /* two-phase super-k-mer kernels with run-time k <= 32, s, m, H <= 8 (any shard size) */
 
 typedef struct sbf_filter sbf_filter; /* opaque; owns its device bit array */
 
@@ -193,14 +195,16 @@ int sbf_insert_marked_dev(sbf_filter *f, const char *d_seq, uint64_t len, const 
 int sbf_query_marked_dev(sbf_filter *f, const char *d_seq, uint64_t len, const uint32_t *d_starts,
                          uint8_t *d_out, void *stream);
 
-/* Choose the kernel family (SBF_VARIANT_*).  SBF_VARIANT_ROLLING and
- * SBF_VARIANT_WIDE fail with SBF_E_INVAL when no such kernel is compiled for
- * the filter's (k,s,m,H) and shard size.  Every family gives bit-identical
+/* Choose the kernel family (SBF_VARIANT_*).  SBF_VARIANT_ROLLING,
+ * SBF_VARIANT_WIDE and SBF_VARIANT_PARAM fail with SBF_E_INVAL when no such
+ * kernel exists for the filter's (k,s,m,H) and shard size (the wide-shard
+ * kernels are compiled for a few parameter sets; the run-time parameter
+ * kernels take k <= 32 and H <= 8).  Every family gives bit-identical
  * filters and answers.  Changing the family resets the tile lengths
  * (sbf_set_tile) to the new family's defaults. */
 int sbf_set_variant(sbf_filter *f, int variant);
 /* The family in effect: SBF_VARIANT_ROLLING (4-word lane kernels),
- * SBF_VARIANT_WIDE or SBF_VARIANT_GENERIC. */
+ * SBF_VARIANT_WIDE, SBF_VARIANT_PARAM or SBF_VARIANT_GENERIC. */
 int sbf_get_variant(const sbf_filter *f);
 
 /* Tile size of the super-k-mer kernels, as k-mers per lane (a tile is 256
@@ -210,7 +214,8 @@ int sbf_get_variant(const sbf_filter *f);
  *   4-word lane kernels, (31,28,16,4) only: insert 32 (default) or 64 k-mers
  *     per lane for the store pass; query 48 (default) or 32, which the
  *     insert's repair walk uses as well;
- *   wide-shard kernels: 16 (default) or 32 for insert and query.
+ *   wide-shard kernels: 16 (default) or 32 for insert and query;
+ *   run-time parameter kernels: 8 (default) or 16 for insert and query.
  * Other values (and any value for the generic kernels) return SBF_E_INVAL.
  * The result does not depend on the tile size.  sbf_get_tile reads the
  * effective lengths back (0 for the generic kernels; pointers may be NULL). */

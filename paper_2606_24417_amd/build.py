@@ -10,7 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsbf.so")
-SOURCES = ["sbf_api.hip", "sbf_server.hip", "kernels_rolling.hip", "kernels_wide.hip", "kernels_generic.hip"]
+SOURCES = ["sbf_api.hip", "sbf_server.hip", "kernels_rolling.hip", "kernels_wide.hip", "kernels_param.hip",
+           "kernels_generic.hip"]
 PROBE_LIB = os.path.join(PKG, "libsbf_probe.so")
 PROBE_SOURCES = ["probe_random_access.hip"]
 

@@ -133,8 +133,9 @@ uint64_t next_pow2(uint64_t x) {
 }
 
 // Kernel family a filter's launches use: the 4-word lane kernels, the
-// wide-shard kernels (any of 4, 8, 16 words) or the generic kernels.
-enum Family { kGenericFamily, kLaneFamily, kWideFamily };
+// wide-shard kernels (any of 4, 8, 16 words), the run-time parameter
+// super-k-mer kernels or the generic kernels.
+enum Family { kGenericFamily, kLaneFamily, kWideFamily, kParamFamily };
 
 Family family(const sbf_filter *f) {
   switch (f->variant) {
@@ -142,9 +143,12 @@ Family family(const sbf_filter *f) {
       return kGenericFamily;
     case SBF_VARIANT_WIDE:
       return sbf::wide_supported(f->g) ? kWideFamily : kGenericFamily;
-    default:  // AUTO and ROLLING: the super-k-mer kernels compiled for the filter
+    case SBF_VARIANT_PARAM:
+      return sbf::param_supported(f->g) ? kParamFamily : kGenericFamily;
+    default:  // AUTO and ROLLING: the fastest super-k-mer kernels for the filter
       if (sbf::rolling_supported(f->g)) return kLaneFamily;
       if (sbf::wide_supported(f->g)) return kWideFamily;
+      if (sbf::param_supported(f->g)) return kParamFamily;
       return kGenericFamily;
   }
 }
@@ -162,6 +166,8 @@ bool lane_len_ok(const sbf_filter *f, uint32_t n, bool insert) {
     }
     case kWideFamily:
       return n == 16 || n == 32;
+    case kParamFamily:
+      return n == 8 || n == 16;
     default:
       return false;
   }
@@ -172,6 +178,7 @@ uint32_t lane_len_effective(const sbf_filter *f, uint32_t n, bool insert) {
   switch (family(f)) {
     case kLaneFamily: return insert ? 32 : 48;
     case kWideFamily: return 16;
+    case kParamFamily: return 8;
     default: return 0;
   }
 }
@@ -250,8 +257,11 @@ int run_insert(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::Launc
     }
     ls.insert_lane_len = f->insert_lane_len;
     ls.query_lane_len = f->query_lane_len;
-    e = family(f) == kWideFamily ? sbf::launch_insert_wide(f->g, f->words, a, mode, ls, st)
-                                 : sbf::launch_insert_rolling(f->g, f->words, a, mode, ls, st);
+    switch (family(f)) {
+      case kWideFamily: e = sbf::launch_insert_wide(f->g, f->words, a, mode, ls, st); break;
+      case kParamFamily: e = sbf::launch_insert_param(f->g, f->words, a, mode, ls, st); break;
+      default: e = sbf::launch_insert_rolling(f->g, f->words, a, mode, ls, st); break;
+    }
   } else {
     e = sbf::launch_insert_generic(f->g, f->words, a, st);
   }
@@ -279,8 +289,11 @@ int run_query(sbf_filter *f, const SeqArgs &a, hipStream_t st, const sbf::Launch
     }
     ls.insert_lane_len = f->insert_lane_len;
     ls.query_lane_len = f->query_lane_len;
-    e = family(f) == kWideFamily ? sbf::launch_query_wide(f->g, f->words, a, ls, st)
-                                 : sbf::launch_query_rolling(f->g, f->words, a, mode, ls, st);
+    switch (family(f)) {
+      case kWideFamily: e = sbf::launch_query_wide(f->g, f->words, a, ls, st); break;
+      case kParamFamily: e = sbf::launch_query_param(f->g, f->words, a, ls, st); break;
+      default: e = sbf::launch_query_rolling(f->g, f->words, a, mode, ls, st); break;
+    }
   } else {
     e = sbf::launch_query_generic(f->g, f->words, a, st);
   }
@@ -926,13 +939,17 @@ int sbf_set_variant(sbf_filter *f, int variant) {
   int rc;
   if ((rc = check_filter(f))) return rc;
   if (variant != SBF_VARIANT_AUTO && variant != SBF_VARIANT_ROLLING && variant != SBF_VARIANT_GENERIC &&
-      variant != SBF_VARIANT_WIDE)
+      variant != SBF_VARIANT_WIDE && variant != SBF_VARIANT_PARAM)
     return set_error(SBF_E_INVAL, "unknown variant %d", variant);
-  if (variant == SBF_VARIANT_ROLLING && !sbf::rolling_supported(f->g) && !sbf::wide_supported(f->g))
-    return set_error(SBF_E_INVAL, "no rolling kernel for k=%u s=%u m=%u H=%u with %u-word shards", f->g.k, f->g.s,
-                     f->g.m, f->g.H, f->g.shard_words);
+  if (variant == SBF_VARIANT_ROLLING && !sbf::rolling_supported(f->g) && !sbf::wide_supported(f->g) &&
+      !sbf::param_supported(f->g))
+    return set_error(SBF_E_INVAL, "no super-k-mer kernel for k=%u s=%u m=%u H=%u with %u-word shards", f->g.k,
+                     f->g.s, f->g.m, f->g.H, f->g.shard_words);
   if (variant == SBF_VARIANT_WIDE && !sbf::wide_supported(f->g))
     return set_error(SBF_E_INVAL, "no wide-shard kernel for k=%u s=%u m=%u H=%u", f->g.k, f->g.s, f->g.m, f->g.H);
+  if (variant == SBF_VARIANT_PARAM && !sbf::param_supported(f->g))
+    return set_error(SBF_E_INVAL, "no run-time parameter kernel for k=%u s=%u m=%u H=%u (needs k <= 32, H <= 8)",
+                     f->g.k, f->g.s, f->g.m, f->g.H);
   f->variant = variant;
   // lane lengths belong to a family: back to the new family's defaults
   f->insert_lane_len = 0;
@@ -946,6 +963,7 @@ int sbf_get_variant(const sbf_filter *f) {
   switch (family(f)) {
     case kLaneFamily: return SBF_VARIANT_ROLLING;
     case kWideFamily: return SBF_VARIANT_WIDE;
+    case kParamFamily: return SBF_VARIANT_PARAM;
     default: return SBF_VARIANT_GENERIC;
   }
 }
@@ -1243,11 +1261,14 @@ int autotune_filter(sbf_filter *f, const Batch &ins, const Batch &q, std::string
     if (!rc) rc = time_it(false, best_q);
     if (!rc) line("generic kernels (nothing to tune): insert %.4f ms, query %.4f ms\n", best_ins, best_q);
   } else {
-    const bool wide = fam == kWideFamily;
+    // the wide-shard and run-time parameter kernels have one query
+    // organisation (two phases, whole lines)
+    const bool wide = fam != kLaneFamily;
+    const char *wide_name = fam == kParamFamily ? "param" : "wide";
     const uint32_t shapes[] = {0, 1, 2, 4, 8};
     // compiled k-mers per lane (the tile is 256 lanes of them)
     std::vector<uint32_t> ins_lens, q_lens;
-    for (uint32_t n : {16u, 32u, 48u, 64u}) {
+    for (uint32_t n : {8u, 16u, 32u, 48u, 64u}) {
       if (lane_len_ok(f, n, true)) ins_lens.push_back(n);
       if (lane_len_ok(f, n, false)) q_lens.push_back(n);
     }
@@ -1293,7 +1314,7 @@ int autotune_filter(sbf_filter *f, const Batch &ins, const Batch &q, std::string
           rc = time_it(false, ms);
           if (rc) break;
           line("query  %-8s %2u k-mers/lane, workgroups/CU %u%s: %.4f ms\n",
-               wide ? "wide" : mode == SBF_QUERY_LANE ? "lane" : mode == SBF_QUERY_LEADER ? "leader" : "direct",
+               wide ? wide_name : mode == SBF_QUERY_LANE ? "lane" : mode == SBF_QUERY_LEADER ? "leader" : "direct",
                mode == SBF_QUERY_LANE ? lane_len_effective(t, len, false) : 16u, sh, sh ? "" : " (one per tile)",
                ms);
           if (ms < best_q) {
@@ -1310,7 +1331,7 @@ int autotune_filter(sbf_filter *f, const Batch &ins, const Batch &q, std::string
            bi_mode == SBF_INSERT_ATOMIC ? "atomic" : "two-pass", lane_len_effective(f, bi_len, true), bi_shape,
            best_ins);
       line("best query: %s, %u k-mers/lane, workgroups/CU %u (%.4f ms)\n",
-           wide ? "wide" : bq_mode == SBF_QUERY_LANE ? "lane" : bq_mode == SBF_QUERY_LEADER ? "leader" : "direct",
+           wide ? wide_name : bq_mode == SBF_QUERY_LANE ? "lane" : bq_mode == SBF_QUERY_LEADER ? "leader" : "direct",
            bq_mode == SBF_QUERY_LANE ? lane_len_effective(f, bq_len, false) : 16u, bq_shape, best_q);
     }
   }

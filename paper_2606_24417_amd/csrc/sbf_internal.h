@@ -69,6 +69,14 @@ hipError_t launch_insert_wide(const Geometry &g, uint64_t *words, const SeqArgs 
                               hipStream_t st);
 hipError_t launch_query_wide(const Geometry &g, const uint64_t *words, const SeqArgs &a, const LaunchShape &ls,
                              hipStream_t st);
+// Run-time parameter super-k-mer kernels (kernels_param.hip): any (k, s, m, H)
+// with m <= k <= 32, s <= k, H <= 8 and shards of 4, 8 or 16 words; query
+// answers as bytes only.
+bool param_supported(const Geometry &g);
+hipError_t launch_insert_param(const Geometry &g, uint64_t *words, const SeqArgs &a, int mode, const LaunchShape &ls,
+                               hipStream_t st);
+hipError_t launch_query_param(const Geometry &g, const uint64_t *words, const SeqArgs &a, const LaunchShape &ls,
+                              hipStream_t st);
 hipError_t launch_insert_generic(const Geometry &g, uint64_t *words, const SeqArgs &a, hipStream_t st);
 hipError_t launch_query_generic(const Geometry &g, const uint64_t *words, const SeqArgs &a, hipStream_t st);
 

@@ -25,6 +25,7 @@ VARIANT_AUTO = 0
 VARIANT_ROLLING = 1
 VARIANT_GENERIC = 2
 VARIANT_WIDE = 3
+VARIANT_PARAM = 4
 INSERT_TWO_PASS = 0
 INSERT_ATOMIC = 1
 QUERY_LANE = 0

@@ -227,9 +227,10 @@ def test_rolling_parameter_sets(k, s, m, H):
 def test_shard_geometry(S, H):
     """Shards of 8 and 16 words (the geometry extension) against the oracle at
     the same geometry, on a record batch with invalid bases: the generic
-    kernels for every H, and the wide-shard super-k-mer kernels where they are
-    compiled (H = 4, 8)."""
-    from paper_2606_24417_amd import VARIANT_GENERIC, VARIANT_ROLLING, VARIANT_WIDE, SBFError
+    kernels for every H, and the super-k-mer kernels where they exist: the
+    wide-shard kernels where they are compiled (H = 4, 8), the run-time
+    parameter kernels for the other H up to 8."""
+    from paper_2606_24417_amd import VARIANT_GENERIC, VARIANT_PARAM, VARIANT_ROLLING, VARIANT_WIDE, SBFError
 
     rng = np.random.default_rng(S * 100 + H)
     ins = random_batch(rng, 80, 3000, 0.002)
@@ -240,16 +241,16 @@ def test_shard_geometry(S, H):
     p = oracle.Params(31, 28, 16, H, bits, shard_words=S)
     F = oracle.insert(p, p.empty(), ins[0], ins[1])
     want = oracle.query(p, F, qs, qo)
-    wide = H in (4, 8)
-    for variant in ([VARIANT_GENERIC, VARIANT_ROLLING] if wide else [VARIANT_GENERIC]):
+    tiled = VARIANT_WIDE if H in (4, 8) else VARIANT_PARAM if H <= 8 else None
+    for variant in ([VARIANT_GENERIC, VARIANT_ROLLING] if tiled else [VARIANT_GENERIC]):
         print("case geometry", S, H, variant, flush=True)
         f = Filter(31, 28, 16, H, bits, shard_words=S)
         assert f.num_bits == p.nshards * S * 64
-        if not wide:
+        if not tiled:
             with pytest.raises(SBFError):
                 f.variant = VARIANT_ROLLING  # no super-k-mer kernel for this H
         f.variant = variant
-        assert f.variant == (VARIANT_WIDE if variant == VARIANT_ROLLING else VARIANT_GENERIC)
+        assert f.variant == (tiled if variant == VARIANT_ROLLING else VARIANT_GENERIC)
         f.insert(dev(ins[0]), dev(ins[1].astype(np.uint64).view(np.int64)))
         ans = f.query(dev(qs), dev(qo.astype(np.uint64).view(np.int64)))
         torch.cuda.synchronize()

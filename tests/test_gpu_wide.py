@@ -131,7 +131,7 @@ def test_wide_persistent_launches(S, wgs):
 
 
 def test_auto_variant_picks_wide_kernels_for_wide_shards():
-    from paper_2606_24417_amd import VARIANT_GENERIC, VARIANT_ROLLING, VARIANT_WIDE, Filter, SBFError
+    from paper_2606_24417_amd import VARIANT_GENERIC, VARIANT_PARAM, VARIANT_ROLLING, VARIANT_WIDE, Filter, SBFError
 
     for S in (8, 16):
         f = Filter(31, 28, 16, 4, 1 << 20, shard_words=S)
@@ -155,11 +155,15 @@ def test_auto_variant_picks_wide_kernels_for_wide_shards():
     with pytest.raises(SBFError):
         f.set_tile(16, 48)
     f.close()
-    # no wide kernel for this parameter set: the generic kernels run
+    # no wide kernel for this parameter set: the run-time parameter kernels run
     f = Filter(31, 27, 16, 4, 1 << 20, shard_words=16)
-    assert f.variant == VARIANT_GENERIC
+    assert f.variant == VARIANT_PARAM
     with pytest.raises(SBFError):
         f.variant = VARIANT_WIDE
+    f.close()
+    # nor a run-time parameter kernel (H > 8): the generic kernels run
+    f = Filter(31, 27, 16, 9, 1 << 20, shard_words=8)
+    assert f.variant == VARIANT_GENERIC
     f.close()
 
 
