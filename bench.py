@@ -37,7 +37,8 @@ PEAK_INT_TOPS = 39.3216      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, 32-bit inte
 # query adds the (k-s+1)*H = 16 bit tests at 2 ops each plus the output 1)
 OPS_PER_KMER = {"insert": 46, "query": 63}
 KERNEL_SOURCES = ["paper_2606_24417_amd/csrc/kernels_rolling.hip", "paper_2606_24417_amd/csrc/kernels_wide.hip",
-                  "paper_2606_24417_amd/csrc/sbf_tiles.h", "paper_2606_24417_amd/csrc/sbf_device.h"]
+                  "paper_2606_24417_amd/csrc/sbf_tiles.h", "paper_2606_24417_amd/csrc/sbf_device.h",
+                  "paper_2606_24417_amd/csrc/sbf_segments.h"]
 
 
 def kernel_source_hash() -> str:
@@ -634,15 +635,22 @@ def bench_host(args):
     print(json.dumps(res), flush=True)
 
 
+FAMILY_NAMES = {1: "lane", 2: "generic", 3: "wide-shard", 4: "run-time parameter"}
+
+
 def bench_sweep(args):
     """(s, m, H) sweep at k = 31 over s in 24..31, m in 12..20, H in 1..8 on the
     in-cache workload (scaled by --scale): per point, the FPR on the negative
     reads, a zero-false-negative check on genome k-mers, and insert and query
-    kernel time.  Then the FPR of independent random 31-mers (each its own
-    record) against filter size at (28, 16, 4)."""
+    kernel time of the run-time parameter kernels (one kernel family over the
+    whole grid, so that times compare parameters) and of the family the
+    library picks by itself (compiled lane or wide-shard kernels where they
+    exist).  Then the shard geometries (4, 8, 16 words) at (28, 16, 4) with
+    every family that runs them.  The FPR against filter size is the
+    fpr_curve workload."""
     import torch
 
-    from paper_2606_24417_amd import Filter
+    from paper_2606_24417_amd import VARIANT_AUTO, VARIANT_PARAM, Filter
 
     t0 = time.perf_counter()
     w = synth.in_cache_workload(args.scale)
@@ -660,84 +668,81 @@ def bench_sweep(args):
     d_q = torch.from_numpy(qs).to(dev)
     d_qoff = torch.from_numpy(qoff.view(np.int64)).to(dev)
     d_out = torch.empty(qs.size, dtype=torch.uint8, device=dev)
+    d_ref = torch.empty(qs.size, dtype=torch.uint8, device=dev)
     fn_len = int(min(ioff[1], 1_000_000))
     d_fn = d_ins[:fn_len]
     d_fn_out = torch.empty(fn_len - k + 1, dtype=torch.uint8, device=dev)
     print("[bench] sweep workload in %.1fs: %d + %d k-mers" % (time.perf_counter() - t0, n_ins_kmers, n_q_kmers),
           file=sys.stderr, flush=True)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def timed(f, out, insert_only=False):
+        ti, tq = [], []
+        for rep in range(3):
+            f.clear(torch.cuda.current_stream())
+            ev[0].record()
+            f.insert(d_ins, d_ioff)
+            ev[1].record()
+            if not insert_only:
+                f.query(d_q, d_qoff, out=out)
+            ev[2].record()
+            torch.cuda.synchronize()
+            ti.append(ev[0].elapsed_time(ev[1]))
+            tq.append(ev[1].elapsed_time(ev[2]))
+        return round(float(np.median(ti)), 4), round(float(np.median(tq)), 4)
+
     rows = []
     grid = [(s_, m_, h_) for s_ in range(24, 32) for m_ in range(12, 21) for h_ in range(1, 9)]
     if args.sweep_points:
         grid = grid[: args.sweep_points]
     for i, (s_, m_, h_) in enumerate(grid):
         f = Filter(k, s_, m_, h_, w["bits"])
-        ti, tq = [], []
-        for rep in range(3):
-            f.clear(torch.cuda.current_stream())
-            ev[0].record()
-            f.insert(d_ins, d_ioff)
-            ev[1].record()
-            f.query(d_q, d_qoff, out=d_out)
-            ev[2].record()
-            torch.cuda.synchronize()
-            ti.append(ev[0].elapsed_time(ev[1]))
-            tq.append(ev[1].elapsed_time(ev[2]))
+        f.variant = VARIANT_PARAM
+        pi, pq = timed(f, d_out)
         f.query(d_fn, out=d_fn_out)
         torch.cuda.synchronize()
         fp = int(d_out[neg0:].sum().item())
         no_fn = bool(int(d_fn_out.sum().item()) == fn_len - k + 1)
-        rows.append({"s": s_, "m": m_, "H": h_, "fpr": fp / max(1, neg_kmers),
-                     "insert_ms": round(float(np.median(ti)), 4), "query_ms": round(float(np.median(tq)), 4),
-                     "variant": "rolling" if f.variant == 1 else "generic", "zero_fn": no_fn})
+        # the insert's other strategy: one atomic OR per segment word
+        f.set_insert_mode(1)
+        pa, _ = timed(f, d_out, insert_only=True)
+        f.set_insert_mode(0)
+        row = {"s": s_, "m": m_, "H": h_, "fpr": fp / max(1, neg_kmers), "param_insert_ms": pi,
+               "param_insert_atomic_ms": pa, "param_query_ms": pq, "zero_fn": no_fn}
+        f.variant = VARIANT_AUTO
+        if f.variant != VARIANT_PARAM:
+            # a compiled family for this point: its own times, and the same
+            # answers as the run-time parameter kernels
+            ai, aq = timed(f, d_ref)
+            row.update({"variant": FAMILY_NAMES[f.variant], "insert_ms": ai, "query_ms": aq,
+                        "answers_equal": bool(torch.equal(d_out, d_ref))})
+        else:
+            row.update({"variant": FAMILY_NAMES[VARIANT_PARAM], "insert_ms": pi, "query_ms": pq})
+        rows.append(row)
         f.close()
         if (i + 1) % 48 == 0:
             print("[bench] sweep %d/%d points" % (i + 1, len(grid)), file=sys.stderr, flush=True)
-    # shard geometry (4, 8, 16 words per shard) at (28, 16, 4): generic kernels
-    # for all three so that their times compare, plus the rolling kernels at 4
+    # shard geometry (4, 8, 16 words per shard) at (28, 16, 4), each with
+    # every family that runs it
     geometry = []
-    for S, variant in ((4, 1), (4, 2), (8, 2), (16, 2)):
-        f = Filter(k, 28, 16, 4, w["bits"], shard_words=S)
-        f.variant = variant
-        ti, tq = [], []
-        for rep in range(3):
-            f.clear(torch.cuda.current_stream())
-            ev[0].record()
-            f.insert(d_ins, d_ioff)
-            ev[1].record()
-            f.query(d_q, d_qoff, out=d_out)
-            ev[2].record()
-            torch.cuda.synchronize()
-            ti.append(ev[0].elapsed_time(ev[1]))
-            tq.append(ev[1].elapsed_time(ev[2]))
-        geometry.append({"shard_words": S, "kernels": "rolling" if variant == 1 else "generic",
-                         "filter_bits": f.num_bits, "fpr": int(d_out[neg0:].sum().item()) / max(1, neg_kmers),
-                         "insert_ms": round(float(np.median(ti)), 4), "query_ms": round(float(np.median(tq)), 4)})
-        f.close()
-    # FPR of independent random 31-mers against filter size, (28, 16, 4)
-    n_rand = int(10_000_000 * min(1.0, args.scale * 10))
-    rs = synth.uniform_acgt(31 * n_rand, 211)  # uniform bases, as the Bloom closed form assumes
-    ro = np.arange(n_rand + 1, dtype=np.uint64) * np.uint64(31)
-    d_rs = torch.from_numpy(rs).to(dev)
-    d_ro = torch.from_numpy(ro.view(np.int64)).to(dev)
-    d_rout = torch.empty(rs.size, dtype=torch.uint8, device=dev)
-    curve = []
-    for lg in range(22, 37, 2):
-        f = Filter(k, 28, 16, 4, 1 << lg)
-        f.insert(d_ins, d_ioff)
-        f.query(d_rs, d_ro, out=d_rout)
-        torch.cuda.synchronize()
-        curve.append({"bits": 1 << lg, "bits_per_kmer": round((1 << lg) / n_ins_kmers, 3),
-                      "fpr": int(d_rout.sum().item()) / n_rand})
-        f.close()
+    for S, variants in ((4, (1, 4, 2)), (8, (3, 4, 2)), (16, (3, 4, 2))):
+        for variant in variants:
+            f = Filter(k, 28, 16, 4, w["bits"], shard_words=S)
+            f.variant = variant
+            ti, tq = timed(f, d_out)
+            geometry.append({"shard_words": S, "kernels": FAMILY_NAMES[variant], "filter_bits": f.num_bits,
+                             "fpr": int(d_out[neg0:].sum().item()) / max(1, neg_kmers), "insert_ms": ti,
+                             "query_ms": tq})
+            f.close()
     all_ok = all(r["zero_fn"] for r in rows)
+    same = all(r.get("answers_equal", True) for r in rows)
     best = min(rows, key=lambda r: r["fpr"])
-    fastest = min(rows, key=lambda r: r["insert_ms"] + r["query_ms"])
+    fastest = min(rows, key=lambda r: r["param_insert_ms"] + r["param_query_ms"])
     res = {"metric": "sweep: FPR and insert/query kernel ms per (s,m,H) at k=31, 16 bits per k-mer",
            "unit": "fpr", "points": len(rows), "zero_false_negatives_everywhere": all_ok,
-           "best_fpr": best, "fastest": fastest,
+           "compiled_and_param_answers_equal": same, "best_fpr": best, "fastest_param": fastest,
            "at_28_16_4": next((r for r in rows if (r["s"], r["m"], r["H"]) == (28, 16, 4)), None),
-           "rows": rows, "geometry": geometry, "fpr_vs_size": curve, "random_kmers": n_rand,
+           "rows": rows, "geometry": geometry,
            "config": {"workload": w["name"] + " (scale %g)" % args.scale, "filter_bits": w["bits"],
                       "insert_kmers": n_ins_kmers, "query_kmers": n_q_kmers, "negative_kmers": neg_kmers}}
     print(json.dumps(res), flush=True)
@@ -1009,7 +1014,7 @@ def measure(args, name, with_cpu):
     # Roofline of the dominant work: the insert is two launches (store pass,
     # then repair walk) unless it runs in atomic mode; the query is one.
     settings = f.get_launch()
-    family = {1: "lane", 2: "generic", 3: "wide-shard", 4: "run-time parameter"}[f.variant]
+    family = FAMILY_NAMES[f.variant]
     tile_i, tile_q = f.get_tile()
     settings.update({"family": family, "shard_words": S, "insert_kmers_per_lane": tile_i,
                      "query_kmers_per_lane": tile_q})

@@ -15,16 +15,23 @@
 //     * then, over the same LDS, the H bit addresses of every s-mer position
 //       (the bit slicing of Section "Optimizations"), one byte each: bit in
 //       the low 6 bits, word group above them;
-//   phase 2, as in the wide-shard kernels: each wave walks 64 consecutive
-//     k-mers per step, finds the runs of valid k-mers with equal shard (the
-//     super-k-mers of Section "Minimizers and Super-k-mers") by ballot and
-//     moves each run's shard with SW/2 lanes, one 16-byte piece each:
-//     insert ORs the run's s-mer bits into the pieces (Algorithm 1: a
-//     read-modify-write with a coherent store, completed by the repair walk,
-//     or 64-bit atomic ORs), query stages the run's shard in LDS and tests
-//     each k-mer's (k-s+1)*H bits there (Algorithm 2).
+//   phase 2 for 4-word shards, as in the lane kernels: lane t walks its LP
+//     k-mers in order, builds each k-mer's mask of (k-s+1)*H bits from the
+//     packed addresses and either extends the open segment (consecutive
+//     valid k-mers with one shard: the super-k-mers of Section "Minimizers
+//     and Super-k-mers") or buffers it and opens the next, the buffered
+//     segments then applied as read-modify-writes by lane pairs (completed by
+//     the repair walk) or atomic ORs (Algorithm 1); the query loads a shard
+//     where it changes and tests each k-mer's mask against it (Algorithm 2);
+//   phase 2 for 8- and 16-word shards, as in the wide-shard kernels: each
+//     wave walks 64 consecutive k-mers per step, finds the runs of valid
+//     k-mers with equal shard by ballot and moves each run's shard with SW/2
+//     lanes, one 16-byte piece each: insert ORs the run's s-mer bits into
+//     the pieces, query stages the run's shard in LDS and tests each k-mer's
+//     bits there.
 // Results are bit-identical to the per-k-mer definition for every parameter
 // set these kernels accept.
+#include "sbf_segments.h"
 #include "sbf_tiles.h"
 
 #include <type_traits>
@@ -138,7 +145,186 @@ __device__ __forceinline__ void param_phase1(ParamTile<LP, WG> &T, const ParamGe
   __syncthreads();
 }
 
-enum ParamInsertMode : int { kParamAtomic = 0, kParamStore = 1 };
+// ---------------------------------------------------------------------------
+// 4-word shards: phase 2 as a lane walk over the lane's LP k-mers.  The bits
+// of a k-mer are those of its s-mers q .. q+z, so consecutive k-mers of one
+// shard share all but one s-mer, and a segment's mask grows by one s-mer per
+// k-mer.
+// ---------------------------------------------------------------------------
+
+// Bits of the s-mer with packed addresses pk over the four words of a 4-word
+// shard: bit b of word t mod 4 for the address byte b of hash index t < H.
+// HMAX (4 or 8) bounds H at compile time; one[t] is 1 for t < H and 0 beyond,
+// so hash indices past H add nothing.
+template <int HMAX>
+__device__ __forceinline__ void smer_bits4(uint64_t pk, const uint32_t (&one)[HMAX], uint64_t (&oh)[4]) {
+  oh[0] = oh[1] = oh[2] = oh[3] = 0;
+#pragma unroll
+  for (int h = 0; h < HMAX; ++h) oh[h & 3] |= (uint64_t)one[h] << ((uint32_t)(pk >> (8 * h)) & 63u);
+}
+
+// Mask of k-mer q: the bits of its s-mers q .. q+z.
+template <int HMAX>
+__device__ __forceinline__ void kmer_mask4(const uint64_t *pos, int q, int z, const uint32_t (&one)[HMAX],
+                                           uint64_t (&A)[4]) {
+  A[0] = A[1] = A[2] = A[3] = 0;
+  for (int j = 0; j <= z; ++j) {
+    uint64_t oh[4];
+    smer_bits4<HMAX>(pos[q + j], one, oh);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) A[w] |= oh[w];
+  }
+}
+
+// Insert: every run of the tile (consecutive valid k-mers with one shard) is
+// written once, by the lane that holds its first k-mer; that lane follows
+// the run past its own k-mers to the run's end in the tile, and the lanes
+// whose first k-mers continue a run from an earlier lane skip them.  With
+// about one run per lane, two buffer slots per lane suffice (and leave LDS
+// for three workgroups per CU).
+template <int LP, int WG, int MODE, int HMAX>
+__global__ __launch_bounds__(WG) void insert_param4_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+                                                           const uint32_t *__restrict__ starts, int aligned16,
+                                                           uint64_t *__restrict__ words, ParamGeo P, TileQueue tq) {
+  using Tl = ParamTile<LP, WG>;
+  __shared__ Tl T;
+  __shared__ SegmentBuffer<(MODE == kAtomic ? 1 : WG), 2> s_buf;
+  __shared__ uint32_t s_next_tile;
+  uint32_t one[HMAX];
+#pragma unroll
+  for (int h = 0; h < HMAX; ++h) one[h] = h < P.H ? 1u : 0u;
+
+  acquire_device();
+  uint64_t tile;
+  for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
+    const uint64_t base = tile * (uint64_t)Tl::TILE;
+    param_phase1<4, LP, WG>(T, P, seq, len, base, starts, aligned16 != 0);
+
+    const int q0 = threadIdx.x * LP;
+    uint64_t seg[4] = {0, 0, 0, 0};  // the open segment's masks
+    uint32_t cur = 0;                // and its shard
+    bool open = false;
+    int nbuf = 0;
+    // k-mers continuing a run that started in an earlier lane
+    bool skip = q0 > 0 && T.valid(q0 - 1);
+    uint32_t prev_sh = q0 > 0 ? T.shard[q0 - 1] : 0u;
+#pragma unroll
+    for (int r = 0; r < LP; ++r) {
+      const int q = q0 + r;
+      const bool v = T.valid(q);
+      const uint32_t sh = T.shard[q];
+      skip = skip && v && sh == prev_sh;
+      prev_sh = sh;
+      if (!skip) {
+        if (open && v && sh == cur) {
+          uint64_t oh[4];
+          smer_bits4<HMAX>(T.pos[q + P.z], one, oh);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) seg[w] |= oh[w];
+        } else {
+          if (open) push_segment<4, MODE>(s_buf, nbuf, words, cur, seg);
+          if (v) {
+            kmer_mask4<HMAX>(T.pos, q, P.z, one, seg);
+            cur = sh;
+          }
+          open = v;
+        }
+      }
+    }
+    if (open) {
+      // the lane's last run may go on into the next lanes' k-mers
+      for (int q = q0 + LP; q < Tl::TILE && T.valid(q) && T.shard[q] == cur; ++q) {
+        uint64_t oh[4];
+        smer_bits4<HMAX>(T.pos[q + P.z], one, oh);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) seg[w] |= oh[w];
+      }
+      push_segment<4, MODE>(s_buf, nbuf, words, cur, seg);
+    }
+    drain_segments<MODE>(s_buf, nbuf, words);
+  }
+}
+
+// Query (and the insert's repair walk): a lane loads a shard where the shard
+// changes along its k-mers and keeps the words for the k-mers after it; each
+// k-mer's mask is built whole (the same work in every lane, where testing
+// each s-mer once would make the lanes that start a segment wait for z more
+// tests at nearly every step).
+template <int LP, int WG, int HMAX, bool REPAIR>
+__global__ __launch_bounds__(WG) void query_param4_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+                                                          const uint32_t *__restrict__ starts, int aligned16,
+                                                          typename std::conditional<REPAIR, uint64_t, const uint64_t>::type *words,
+                                                          ParamGeo P, uint8_t *__restrict__ out, uint64_t n_out,
+                                                          int out_aligned8, TileQueue tq) {
+  using Tl = ParamTile<LP, WG>;
+  static_assert(LP % 8 == 0 && LP <= 32, "whole 8-byte answer groups, answer bits in one 32-bit word");
+  __shared__ Tl T;
+  __shared__ uint32_t s_next_tile;
+  uint32_t one[HMAX];
+#pragma unroll
+  for (int h = 0; h < HMAX; ++h) one[h] = h < P.H ? 1u : 0u;
+
+  acquire_device();
+  uint64_t tile;
+  for (bool first = true; next_tile(tq, &s_next_tile, first, tile); first = false) {
+    const uint64_t base = tile * (uint64_t)Tl::TILE;
+    param_phase1<4, LP, WG>(T, P, seq, len, base, starts, aligned16 != 0);
+
+    const int q0 = threadIdx.x * LP;
+    uint32_t ans = 0;
+    uint64_t got[4] = {0, 0, 0, 0};
+    uint32_t cur = 0;
+    bool have = false;
+#pragma unroll
+    for (int r = 0; r < LP; ++r) {
+      const int q = q0 + r;
+      const uint32_t sh = T.shard[q];
+      if (T.valid(q)) {
+        if (!have || sh != cur) {
+          const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)sh);
+          const uint4 lo = p[0], hi = p[1];
+          got[0] = ((uint64_t)lo.y << 32) | lo.x;
+          got[1] = ((uint64_t)lo.w << 32) | lo.z;
+          got[2] = ((uint64_t)hi.y << 32) | hi.x;
+          got[3] = ((uint64_t)hi.w << 32) | hi.z;
+          cur = sh;
+          have = true;
+        }
+        uint64_t A[4];
+        kmer_mask4<HMAX>(T.pos, q, P.z, one, A);
+        uint64_t miss[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) miss[w] = A[w] & ~got[w];
+        if constexpr (REPAIR) {
+          // OR the bits a racing store dropped into the shard and into the
+          // cached words, so that later k-mers of the lane do not repeat them
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            if (miss[w]) atomic_or64(words + 4ull * (uint64_t)sh + w, miss[w]);
+            got[w] |= miss[w];
+          }
+        } else {
+          if ((miss[0] | miss[1] | miss[2] | miss[3]) == 0) ans |= 1u << r;
+        }
+      }
+    }
+    if constexpr (!REPAIR) {
+      // answer bytes: four bits x spread to bytes by x * 0x204081
+      const uint64_t pos0 = base + (uint64_t)q0;
+      if (out_aligned8 && pos0 + LP <= n_out) {
+#pragma unroll
+        for (int c = 0; c < LP / 8; ++c) {
+          const uint32_t b = ans >> (8 * c);
+          *reinterpret_cast<uint2 *>(out + pos0 + 8 * c) =
+              make_uint2(((b & 0xFu) * 0x204081u) & 0x01010101u, (((b >> 4) & 0xFu) * 0x204081u) & 0x01010101u);
+        }
+      } else {
+        for (int r = 0; r < LP; ++r)
+          if (pos0 + r < n_out) out[pos0 + r] = (uint8_t)((ans >> r) & 1u);
+      }
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Insert.  Lane (run j, piece p) of a round owns words 2p and 2p+1 of run j's
@@ -206,7 +392,7 @@ __global__ __launch_bounds__(WG) void insert_param_kernel(const uint8_t *__restr
           const int b = (int)(span >> 16);
           uint64_t *line = words + (uint64_t)rsh * SW + 2 * p;
           uint64_t o0 = 0, o1 = 0;
-          if constexpr (MODE == kParamStore) {
+          if constexpr (MODE == kStore) {
             const uint4 piece = *reinterpret_cast<const uint4 *>(line);
             o0 = ((uint64_t)piece.y << 32) | piece.x;
             o1 = ((uint64_t)piece.w << 32) | piece.z;
@@ -227,7 +413,7 @@ __global__ __launch_bounds__(WG) void insert_param_kernel(const uint8_t *__restr
               }
             }
           }
-          if constexpr (MODE == kParamStore) {
+          if constexpr (MODE == kStore) {
             if ((o0 | m0) != o0 || (o1 | m1) != o1) store_pair_coherent(line, o0 | m0, o1 | m1);
           } else {
             if (m0) atomic_or64(line, m0);
@@ -348,24 +534,57 @@ ParamGeo param_geo(const Geometry &g) {
   return P;
 }
 
-template <int SW, int LP>
-hipError_t insert_param(const ParamGeo &P, uint64_t *words, const SeqArgs &a, int mode, const LaunchShape &ls,
-                        hipStream_t st) {
-  if (a.len < (uint64_t)P.k) return hipSuccess;
+template <int LP, int HMAX>
+hipError_t insert_param4(const ParamGeo &P, uint64_t *words, const SeqArgs &a, int mode, const LaunchShape &ls,
+                         hipStream_t st) {
   const uint64_t nk = a.len - P.k + 1;
   const uint64_t tile = (uint64_t)LP * kParamWG;
   const uint64_t ntiles = (nk + tile - 1) / tile;
   const int aligned = ((uintptr_t)a.seq & 15u) == 0;
   if (mode == kInsertAtomicMode) {
-    SBF_LAUNCH_TILES((insert_param_kernel<SW, LP, kParamWG, kParamAtomic>), kParamWG, ntiles, 0, a.seq, a.len,
+    SBF_LAUNCH_TILES((insert_param4_kernel<LP, kParamWG, kAtomic, HMAX>), kParamWG, ntiles, 0, a.seq, a.len,
                      a.starts, aligned, words, P);
     return hipSuccess;
   }
-  SBF_LAUNCH_TILES((insert_param_kernel<SW, LP, kParamWG, kParamStore>), kParamWG, ntiles, 0, a.seq, a.len,
-                   a.starts, aligned, words, P);
-  SBF_LAUNCH_TILES((query_param_kernel<SW, LP, kParamWG, true>), kParamWG, ntiles, 1, a.seq, a.len, a.starts, aligned,
-                   words, P, (uint8_t *)nullptr, nk);
+  SBF_LAUNCH_TILES((insert_param4_kernel<LP, kParamWG, kStore, HMAX>), kParamWG, ntiles, 0, a.seq, a.len, a.starts,
+                   aligned, words, P);
+  SBF_LAUNCH_TILES((query_param4_kernel<LP, kParamWG, HMAX, true>), kParamWG, ntiles, 1, a.seq, a.len, a.starts,
+                   aligned, words, P, (uint8_t *)nullptr, nk, 0);
   return hipSuccess;
+}
+
+template <int LP, int HMAX>
+hipError_t query_param4(const ParamGeo &P, const uint64_t *words, const SeqArgs &a, const LaunchShape &ls,
+                        hipStream_t st) {
+  const uint64_t tile = (uint64_t)LP * kParamWG;
+  const int aligned = ((uintptr_t)a.seq & 15u) == 0;
+  SBF_LAUNCH_TILES((query_param4_kernel<LP, kParamWG, HMAX, false>), kParamWG, (a.n_out + tile - 1) / tile, 2, a.seq,
+                   a.len, a.starts, aligned, words, P, a.out, a.n_out, (int)(((uintptr_t)a.out & 7u) == 0));
+  return hipSuccess;
+}
+
+template <int SW, int LP>
+hipError_t insert_param(const ParamGeo &P, uint64_t *words, const SeqArgs &a, int mode, const LaunchShape &ls,
+                        hipStream_t st) {
+  if (a.len < (uint64_t)P.k) return hipSuccess;
+  if constexpr (SW == 4) {
+    return P.H <= 4 ? insert_param4<LP, 4>(P, words, a, mode, ls, st) : insert_param4<LP, 8>(P, words, a, mode, ls, st);
+  } else {
+    const uint64_t nk = a.len - P.k + 1;
+    const uint64_t tile = (uint64_t)LP * kParamWG;
+    const uint64_t ntiles = (nk + tile - 1) / tile;
+    const int aligned = ((uintptr_t)a.seq & 15u) == 0;
+    if (mode == kInsertAtomicMode) {
+      SBF_LAUNCH_TILES((insert_param_kernel<SW, LP, kParamWG, kAtomic>), kParamWG, ntiles, 0, a.seq, a.len, a.starts,
+                       aligned, words, P);
+      return hipSuccess;
+    }
+    SBF_LAUNCH_TILES((insert_param_kernel<SW, LP, kParamWG, kStore>), kParamWG, ntiles, 0, a.seq, a.len, a.starts,
+                     aligned, words, P);
+    SBF_LAUNCH_TILES((query_param_kernel<SW, LP, kParamWG, true>), kParamWG, ntiles, 1, a.seq, a.len, a.starts,
+                     aligned, words, P, (uint8_t *)nullptr, nk);
+    return hipSuccess;
+  }
 }
 
 template <int SW, int LP>
@@ -373,11 +592,15 @@ hipError_t query_param(const ParamGeo &P, const uint64_t *words, const SeqArgs &
                        hipStream_t st) {
   if (a.n_out == 0) return hipSuccess;
   if (a.packed) return hipErrorInvalidValue;  // answers as bytes only
-  const uint64_t tile = (uint64_t)LP * kParamWG;
-  const int aligned = ((uintptr_t)a.seq & 15u) == 0;
-  SBF_LAUNCH_TILES((query_param_kernel<SW, LP, kParamWG, false>), kParamWG, (a.n_out + tile - 1) / tile, 2, a.seq,
-                   a.len, a.starts, aligned, words, P, a.out, a.n_out);
-  return hipSuccess;
+  if constexpr (SW == 4) {
+    return P.H <= 4 ? query_param4<LP, 4>(P, words, a, ls, st) : query_param4<LP, 8>(P, words, a, ls, st);
+  } else {
+    const uint64_t tile = (uint64_t)LP * kParamWG;
+    const int aligned = ((uintptr_t)a.seq & 15u) == 0;
+    SBF_LAUNCH_TILES((query_param_kernel<SW, LP, kParamWG, false>), kParamWG, (a.n_out + tile - 1) / tile, 2, a.seq,
+                     a.len, a.starts, aligned, words, P, a.out, a.n_out);
+    return hipSuccess;
+  }
 }
 
 template <int SW>
