@@ -1047,11 +1047,11 @@ def measure(args, name, with_cpu):
         # write through to the coherence point; the probe does the same)
         probe = {}
         sb = 8 * S
-        for key, mode, line_mode in (("read", 0, 5), ("rmw", 7, 8)):
+        for access, mode, line_mode in (("read", 0, 5), ("rmw", 7, 8)):
             best, _ = probe_ceiling(8192, mode, sb)
             best_l, _ = probe_ceiling(8192, line_mode, sb)
             best_l["lanes_per_shard"] = sb // 16
-            probe[key] = best if best["G_per_s"] >= best_l["G_per_s"] else best_l
+            probe[access] = best if best["G_per_s"] >= best_l["G_per_s"] else best_l
         print("[bench] random-access ceilings (8 GiB, %d B): %s" % (sb, json.dumps(probe)), file=sys.stderr, flush=True)
 
     def roofline(part, ms, kmers, launches):
