@@ -207,3 +207,42 @@ def test_autotuner_covers_tile_lengths():
     # the tuned filter still holds exactly the inserted k-mers
     assert_same(f.get_bits(), F, "filter words after autotuning")
     f.close()
+
+
+@pytest.mark.parametrize("S", [4, 16])
+def test_unaligned_input_and_output_and_host_path(S):
+    """Sequence and answer buffers at odd device addresses (byte loads and
+    byte stores instead of 16- and 8-byte ones), a single sequence (no
+    record starts), and the host entry points (pinned staging, chunked)."""
+    rng = np.random.default_rng(500 + S)
+    params = (31, 25, 15, 6, 1 << 17)
+    ins, q = mixed(rng, 900)
+    p = oracle.Params(*params, shard_words=S)
+    F = oracle.insert(p, p.empty(), *ins)
+    want = oracle.query(p, F, *q)
+    f = param_filter(*params, S)
+    # insert from an odd address
+    buf = torch.zeros(ins[0].size + 3, dtype=torch.uint8, device="cuda")
+    buf[3:] = dev(ins[0])
+    f.insert(buf[3:], doff(ins[1]))
+    torch.cuda.synchronize()
+    assert_same(f.get_bits(), F, "filter words (unaligned sequence)")
+    # answers into an odd address
+    qs = torch.zeros(q[0].size + 5, dtype=torch.uint8, device="cuda")
+    qs[5:] = dev(q[0])
+    out = torch.full((q[0].size + 1,), 9, dtype=torch.uint8, device="cuda")
+    print("case param unaligned", S, flush=True)
+    f.query(qs[5:], doff(q[1]), out=out[1:])
+    torch.cuda.synchronize()
+    assert_same(out[1:].cpu().numpy(), want, "answers (unaligned output)")
+    assert int(out[0].item()) == 9
+    # a single sequence: len - k + 1 answers
+    one = q[0][: int(q[1][1])]
+    if one.size >= params[0]:
+        got1 = f.query(dev(one)).cpu().numpy()
+        assert_same(got1, oracle.query(p, F, one)[: one.size - params[0] + 1], "single-sequence answers")
+    # host entry points, staging in small chunks
+    f.set_staging_bytes(1 << 16)
+    got_h = f.query(q[0], q[1])
+    assert_same(np.asarray(got_h), want, "answers (host path)")
+    f.close()

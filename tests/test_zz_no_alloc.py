@@ -73,6 +73,41 @@ def test_noalloc_query_matches_allocating_query(launch):
     f.close()
 
 
+# every kernel family behind the same entry point: compiled lane kernels at
+# their default (above), run-time parameter kernels (4- and 8-word shards),
+# wide-shard kernels and the generic kernels
+@pytest.mark.parametrize("params,S,variant", [((31, 26, 14, 5), 4, 0), ((31, 27, 17, 3), 8, 4),
+                                              ((31, 28, 16, 4), 16, 3), ((31, 28, 16, 4), 4, 2)])
+def test_noalloc_query_every_family(params, S, variant):
+    from paper_2606_24417_amd import Filter
+
+    bits = 1 << 22
+    ins = synth.uniform_acgt(2_000_000, 17)
+    f = Filter(*params, bits, shard_words=S)
+    if variant:
+        f.variant = variant
+    f.set_launch(1, 1)
+    f.insert(_dev(ins))
+    p = oracle.Params(*params, bits, shard_words=S)
+    F = oracle.insert(p, p.empty(), ins)
+    for seed, n_reads, lo, hi in [(21, 8000, 20, 400), (22, 500, 1, 200)]:
+        seq, off = _batch(seed, n_reads, lo, hi)
+        half = int(off[n_reads // 2])
+        seq[:half] = ins[:half]
+        print("case noalloc family params=%s S=%d variant=%d seed=%d" % (params, S, f.variant, seed), flush=True)
+        d_seq, d_off = _dev(seq), _off(off)
+        out_na = torch.full((seq.size,), 7, dtype=torch.uint8, device="cuda")
+        f.query_batch_dev_noalloc(d_seq, d_off, out_na)
+        out_ref = f.query(d_seq, d_off)
+        torch.cuda.synchronize()
+        got, ref = out_na.cpu().numpy(), out_ref.cpu().numpy()
+        want = oracle.query(p, F, seq, off)
+        assert np.array_equal(got, ref)
+        assert np.array_equal(got, want)
+        assert want[:half].sum() > 0
+    f.close()
+
+
 def test_noalloc_query_rejects_batches_above_its_scratch():
     from paper_2606_24417_amd import Filter, SBFError, SBF_E_INVAL
 
