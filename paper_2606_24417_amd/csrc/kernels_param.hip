@@ -8,10 +8,13 @@
 //     (consecutive lanes, consecutive positions):
 //     * each k-mer's validity (one ballot per 64 k-mers);
 //     * the minimizer hash h_M of every m-mer position of the tile, once,
-//       into LDS; doubling turns them into running minima (after level j,
-//       slot p holds the minimum over positions p .. p + 2^j - 1), and the
-//       minimum over a k-mer's w = k-m+1 m-mers is the smaller of the two
-//       overlapping windows of 2^j <= w positions at its two ends;
+//       into LDS, each from a 64-bit base window of the staged codes;
+//     * then, per lane over its own LP consecutive k-mers, the minimum of
+//       each k-mer's w = k-m+1 m-mer hashes: for w >= LP the LP windows
+//       share positions LP-1 .. w-1, so one minimum over those, suffix
+//       minima of the positions before and prefix minima of those after
+//       give all LP windows (about (w + 3 LP) / LP compares per k-mer), and
+//       the k-mer's shard;
 //     * then, over the same LDS, the H bit addresses of every s-mer position
 //       (the bit slicing of Section "Optimizations"), one byte each: bit in
 //       the low 6 bits, word group above them;
@@ -46,7 +49,6 @@ struct ParamGeo {
   int k;       // k-mer length (<= 32)
   int z;       // k - s: s-mers per k-mer minus one
   int w;       // k - m + 1: m-mers per k-mer
-  int lvl;     // 2^lvl <= w < 2^(lvl+1)
   int H;       // hash indices per s-mer (<= 8)
   int slice;   // 64 / H: hash bits per index
   int m_shift; // 64 - 2m: an m-mer from a 64-bit base window
@@ -55,20 +57,25 @@ struct ParamGeo {
 };
 
 // LDS of one tile: the staged sequence, one 64-bit slot per m-mer / s-mer
-// position (m-mer hashes and their running minima, then the s-mers' packed
-// bit addresses), and per k-mer its shard and validity.
+// position (m-mer hashes, then the s-mers' packed bit addresses), and per
+// k-mer its shard and validity.  The m-mer hashes are stored one slot apart
+// every LP positions (hpos), so that lanes reading their own LP consecutive
+// positions hit different banks.
 template <int LP, int WG>
 struct ParamTile {
   static constexpr int TILE = WG * LP;
   static constexpr int NPOS = TILE + kParamKMax;  // w - 1 and z are below 32
+  static constexpr int NSLOT = NPOS + NPOS / LP + 1;
   static constexpr int NGRAN = TILE / 16 + 4;      // windows reach base TILE + 62
   uint32_t codes[NGRAN];
   uint32_t vb[NGRAN];
-  uint64_t pos[NPOS];
+  uint64_t pos[NSLOT];
   uint32_t shard[TILE];
   uint64_t kv[TILE / 64];  // bit q % 64 of word q / 64: k-mer q is valid
 
   __device__ __forceinline__ bool valid(int q) const { return (kv[q >> 6] >> (q & 63)) & 1ull; }
+  // slot of the m-mer hash of position j
+  static __device__ __forceinline__ int hpos(int j) { return j + j / LP; }
 };
 
 // Bases j .. j+31 of the staged tile as one 64-bit value, first base most
@@ -98,44 +105,54 @@ __device__ __forceinline__ void param_phase1(ParamTile<LP, WG> &T, const ParamGe
                                              const uint8_t *__restrict__ seq, uint64_t len, uint64_t base,
                                              const uint32_t *__restrict__ starts, bool aligned16) {
   using Tl = ParamTile<LP, WG>;
-  constexpr int NV = (Tl::NPOS + WG - 1) / WG;  // positions per lane
   // address byte: bit (6 bits), then log2(SW/4) bits of word group
   constexpr uint32_t AMASK = 16u * SW - 1u;
   stage_granules<WG>(seq, len, base, starts, aligned16, Tl::NGRAN, T.codes, T.vb);
   __syncthreads();
   const int t = threadIdx.x;
-  // validity: a wave judges 64 consecutive k-mers per iteration
+  // validity: a wave judges 64 consecutive k-mers per ballot
   for (int q = t; q < Tl::TILE; q += WG) {
     const uint64_t b = __ballot(kmer_ok(T.vb, q, P.k));
     if ((t & 63) == 0) T.kv[q >> 6] = b;
   }
   // m-mer hashes of positions 0 .. TILE + w - 2
-  int n = Tl::TILE + P.w - 1;
-  for (int j = t; j < n; j += WG) T.pos[j] = minimizer_hash(base_window(T.codes, j) >> P.m_shift);
+  for (int j = t; j < Tl::TILE + P.w - 1; j += WG) T.pos[Tl::hpos(j)] = minimizer_hash(base_window(T.codes, j) >> P.m_shift);
   __syncthreads();
-  // doubling: after level l slot j holds the minimum over j .. j + 2^(l+1) - 1
-  for (int l = 0; l < P.lvl; ++l) {
-    const int d = 1 << l;
-    n -= d;
-    uint64_t v[NV];
+  // minimizer of each of the lane's k-mers q0 .. q0+LP-1 (window of
+  // positions q .. q+w-1)
+  {
+    const int q0 = t * LP;
+    const uint64_t *H = T.pos;
+    uint64_t win[LP];
+    if (P.w >= LP) {
+      // positions q0+LP-1 .. q0+w-1 lie in every window
+      uint64_t mid = H[Tl::hpos(q0 + LP - 1)];
+      for (int j = q0 + LP; j < q0 + P.w; ++j) mid = umin64(mid, H[Tl::hpos(j)]);
+      // window r adds positions q0+r .. q0+LP-2 (suffix) and q0+w .. q0+w+r-1 (prefix)
+      uint64_t suf = ~0ull, pre = ~0ull;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int j = t + i * WG;
-      if (j < n) v[i] = umin64(T.pos[j], T.pos[j + d]);
-    }
-    __syncthreads();
+      for (int r = LP - 1; r >= 0; --r) {
+        if (r < LP - 1) suf = umin64(suf, H[Tl::hpos(q0 + r)]);
+        win[r] = umin64(suf, mid);
+      }
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      const int j = t + i * WG;
-      if (j < n) T.pos[j] = v[i];
+      for (int r = 1; r < LP; ++r) {
+        pre = umin64(pre, H[Tl::hpos(q0 + P.w + r - 1)]);
+        win[r] = umin64(win[r], pre);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < LP; ++r) {
+        uint64_t m = ~0ull;
+        for (int j = q0 + r; j < q0 + r + P.w; ++j) m = umin64(m, H[Tl::hpos(j)]);
+        win[r] = m;
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < LP; ++r) T.shard[q0 + r] = (uint32_t)win[r] & P.shard_mask;
   }
-  // minimizer of k-mer q: the two windows of 2^lvl positions at its ends
-  const int tail = P.w - (1 << P.lvl);
-  for (int q = t; q < Tl::TILE; q += WG) T.shard[q] = (uint32_t)umin64(T.pos[q], T.pos[q + tail]) & P.shard_mask;
   __syncthreads();
-  // packed bit addresses of s-mer positions 0 .. TILE + z - 1
+  // packed bit addresses of s-mer positions 0 .. TILE + z - 1, over the hashes
   for (int j = t; j < Tl::TILE + P.z; j += WG) {
     const uint64_t g = smer_hash(base_window(T.codes, j) >> P.s_shift);
     uint64_t pk = 0;
@@ -251,7 +268,7 @@ __global__ __launch_bounds__(WG) void insert_param4_kernel(const uint8_t *__rest
 // each s-mer once would make the lanes that start a segment wait for z more
 // tests at nearly every step).
 template <int LP, int WG, int HMAX, bool REPAIR>
-__global__ __launch_bounds__(WG) void query_param4_kernel(const uint8_t *__restrict__ seq, uint64_t len,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void query_param4_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                           const uint32_t *__restrict__ starts, int aligned16,
                                                           typename std::conditional<REPAIR, uint64_t, const uint64_t>::type *words,
                                                           ParamGeo P, uint8_t *__restrict__ out, uint64_t n_out,
@@ -524,8 +541,6 @@ ParamGeo param_geo(const Geometry &g) {
   P.k = (int)g.k;
   P.z = (int)(g.k - g.s);
   P.w = (int)(g.k - g.m + 1);
-  P.lvl = 0;
-  while ((2 << P.lvl) <= P.w) ++P.lvl;
   P.H = (int)g.H;
   P.slice = 64 / (int)g.H;
   P.m_shift = 64 - 2 * (int)g.m;
