@@ -900,7 +900,9 @@ def main():
             "query_kmers_per_s", "insert_ms_median", "query_ms_median", "query_present", "oracle_check",
             "roofline", "roofline_other")}
     print(json.dumps(res), flush=True)
-    if not all(r.get("oracle_check", {}).get("ok", True) for r in (res, res.get("in_cache", {}))):
+    # a mismatch with the stored oracle results fails the run; a workload
+    # without stored results (another filter size, say) only reports so
+    if any(r.get("oracle_check", {}).get("ok") is False for r in (res, res.get("in_cache", {}))):
         sys.exit(1)
 
 
