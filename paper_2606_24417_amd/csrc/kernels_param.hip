@@ -4,11 +4,11 @@
 // s-mer windows for a few compiled parameter sets; the paper's parameter
 // study (Section "Parameter Selection") spans hundreds of sets, so these
 // kernels take k, s, m and H at run time and keep the super-k-mer work:
-//   phase 1, per tile of WG x LP k-mers, one position per lane at a time
-//     (consecutive lanes, consecutive positions):
-//     * each k-mer's validity (one ballot per 64 k-mers);
-//     * the minimizer hash h_M of every m-mer position of the tile, once,
-//       into LDS, each from a 64-bit base window of the staged codes;
+//   phase 1, per tile of WG x LP k-mers:
+//     * each k-mer's validity (one ballot per 64 k-mers) and the minimizer
+//       hash h_M of every m-mer position of the tile, once, into LDS, each
+//       from a 64-bit base window of the staged codes (one position per lane
+//       at a time: consecutive lanes, consecutive positions);
 //     * then, per lane over its own LP consecutive k-mers, the minimum of
 //       each k-mer's w = k-m+1 m-mer hashes: for w >= LP the LP windows
 //       share positions LP-1 .. w-1, so one minimum over those, suffix
@@ -19,13 +19,14 @@
 //       (the bit slicing of Section "Optimizations"), one byte each: bit in
 //       the low 6 bits, word group above them;
 //   phase 2 for 4-word shards, as in the lane kernels: lane t walks its LP
-//     k-mers in order, builds each k-mer's mask of (k-s+1)*H bits from the
-//     packed addresses and either extends the open segment (consecutive
-//     valid k-mers with one shard: the super-k-mers of Section "Minimizers
-//     and Super-k-mers") or buffers it and opens the next, the buffered
-//     segments then applied as read-modify-writes by lane pairs (completed by
-//     the repair walk) or atomic ORs (Algorithm 1); the query loads a shard
-//     where it changes and tests each k-mer's mask against it (Algorithm 2);
+//     k-mers in order.  Insert: each run of valid k-mers with one shard (the
+//     super-k-mers of Section "Minimizers and Super-k-mers") is written once,
+//     by the lane holding its first k-mer, whose mask starts with that
+//     k-mer's (k-s+1)*H bits and adds one s-mer per following k-mer, also
+//     past the lane's own k-mers; finished runs are buffered and applied as
+//     read-modify-writes by lane pairs (completed by the repair walk) or as
+//     atomic ORs (Algorithm 1).  Query: a lane loads a shard where it changes
+//     and tests each k-mer's mask against it (Algorithm 2);
 //   phase 2 for 8- and 16-word shards, as in the wide-shard kernels: each
 //     wave walks 64 consecutive k-mers per step, finds the runs of valid
 //     k-mers with equal shard by ballot and moves each run's shard with SW/2
