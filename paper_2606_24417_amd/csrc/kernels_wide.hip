@@ -68,8 +68,9 @@ __device__ __forceinline__ uint32_t addr_byte(wide_pack_t<H> pk, int t) {
 }
 
 // LDS of one tile: the staged sequence, then per k-mer its shard and
-// validity and per s-mer its packed addresses.
-template <int K, int S, int H, int LP, int WG>
+// validity and per s-mer its packed addresses.  The staged sequence is only
+// read in phase 1, so phase 2 may reuse its bytes and SCR more (scratch).
+template <int K, int S, int H, int LP, int WG, int SCR = 1>
 struct WideTile {
   static constexpr int Z = K - S;
   static constexpr int TILE = WG * LP;
@@ -77,8 +78,13 @@ struct WideTile {
   static constexpr int NGW = lane_granules<K, LP>();
   static constexpr int NGRAN = (WG - 1) * GPL + NGW;
   static constexpr int KVW = (LP + 31) / 32;  // validity words per lane
-  uint32_t codes[NGRAN];
-  uint32_t vb[NGRAN];
+  union {
+    struct {
+      uint32_t codes[NGRAN];
+      uint32_t vb[NGRAN];
+    };
+    uint2 scratch[SCR];
+  };
   uint32_t shard[TILE];
   wide_pack_t<H> bits[TILE + Z];
   uint32_t kv[WG * KVW];
@@ -92,11 +98,11 @@ struct WideTile {
 // Phase 1: stage the tile starting at k-mer `base` and fill shard, kv and
 // bits (lane t: k-mers and s-mers t*LP .. t*LP+LP-1, the last lane also the
 // z s-mers after the tile).
-template <int K, int S, int M, int H, int SW, int LP, int WG>
-__device__ __forceinline__ void wide_phase1(WideTile<K, S, H, LP, WG> &T, const uint8_t *__restrict__ seq,
+template <int K, int S, int M, int H, int SW, int LP, int WG, int SCR>
+__device__ __forceinline__ void wide_phase1(WideTile<K, S, H, LP, WG, SCR> &T, const uint8_t *__restrict__ seq,
                                             uint64_t len, uint64_t base, const uint32_t *__restrict__ starts,
                                             bool aligned16, uint32_t shard_mask) {
-  using Tl = WideTile<K, S, H, LP, WG>;
+  using Tl = WideTile<K, S, H, LP, WG, SCR>;
   constexpr int W = K - M + 1;
   constexpr int Z = K - S;
   stage_granules<WG>(seq, len, base, starts, aligned16, Tl::NGRAN, T.codes, T.vb);
@@ -275,19 +281,25 @@ __global__ __launch_bounds__(WG) void query_wide_kernel(const uint8_t *__restric
                                                         typename std::conditional<REPAIR, uint64_t, const uint64_t>::type *words,
                                                         uint32_t shard_mask, uint8_t *__restrict__ out,
                                                         uint64_t n_out, TileQueue tq) {
-  using Tl = WideTile<K, S, H, LP, WG>;
   constexpr int Z = K - S;
   constexpr int NWAVES = WG / 64;
-  constexpr int PER_WAVE = Tl::TILE / NWAVES;
   constexpr int LPR = SW / 2;
   constexpr int RPR = 64 / LPR;
-  constexpr int PASS = 16;  // run lines staged at once per wave
+  // run lines staged at once per wave: 8 for 16-word shards, so that the
+  // tile (38.9 KB with 256 lanes x 16 k-mers) leaves LDS for four
+  // workgroups per CU (with 16 lines, three fit; the query and repair walk
+  // ran 19% slower)
+  constexpr int PASS = SW == 16 ? 8 : 16;
   constexpr int HALF = SW / 2;
+  // one staged line per run (SW words as dword pairs), over the staged
+  // sequence, which phase 1 no longer needs
+  using Tl = WideTile<K, S, H, LP, WG, NWAVES * PASS * SW>;
+  constexpr int PER_WAVE = Tl::TILE / NWAVES;
 
   __shared__ Tl T;
   __shared__ uint32_t s_run_shard[NWAVES][64];
-  __shared__ uint2 s_line[NWAVES][PASS][SW];  // one staged line per run: SW words as dword pairs
   __shared__ uint32_t s_next_tile;
+  uint2 (*s_line)[PASS][SW] = reinterpret_cast<uint2 (*)[PASS][SW]>(T.scratch);
 
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
