@@ -165,18 +165,21 @@ enum WideInsertMode : int { kWideAtomic = 0, kWideStore = 1 };
 
 // ---------------------------------------------------------------------------
 // Insert.  Lane (run j, piece p) of a round owns words 2p and 2p+1 of run j's
-// shard: sectors e = 2p mod 4 and e+1, group p / 2 (for SW = 8, 16).  So of
-// each s-mer only hash indices t with (t mod 4) in {e, e+1} can reach them:
-// t = 4i + u + e (u = 0, 1), a lane-dependent byte of the packed addresses.
+// shard.  The run's SW/2 lanes split its s-mers between them (every SW/2-th
+// one each) and OR each s-mer's H bits into the run's line buffer in LDS with
+// LDS atomics; each lane then takes its two words from the buffer and applies
+// them to its piece of the shard.
 // ---------------------------------------------------------------------------
 template <int K, int S, int M, int H, int SW, int LP, int WG, int MODE>
 __global__ __launch_bounds__(WG) void insert_wide_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                          const uint32_t *__restrict__ starts, int aligned16,
                                                          uint64_t *__restrict__ words, uint32_t shard_mask,
                                                          TileQueue tq) {
-  using Tl = WideTile<K, S, H, LP, WG>;
   constexpr int Z = K - S;
   constexpr int NWAVES = WG / 64;
+  // line buffers of a round's runs (two words per lane, 1 KB per wave), over
+  // the tile's staged sequence, which phase 2 no longer reads
+  using Tl = WideTile<K, S, H, LP, WG, NWAVES * 128>;
   constexpr int PER_WAVE = Tl::TILE / NWAVES;  // 64 * LP k-mers
   constexpr int LPR = SW / 2;                  // lanes per run
   constexpr int RPR = 64 / LPR;                // runs per round
@@ -192,10 +195,12 @@ __global__ __launch_bounds__(WG) void insert_wide_kernel(const uint8_t *__restri
   const int lane = threadIdx.x & 63;
   const int q0 = wave * PER_WAVE;
   const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-  // this lane's piece of a run's line and the hash indices that reach it
+  // this lane's piece of a run's line: words 2p, 2p+1
   const int p = lane % LPR;
-  const int e = (2 * p) & 3;                // sector of word 2p (0 or 2)
-  const uint32_t grp = (uint32_t)(p >> 1);  // word group of words 2p, 2p+1
+  const int slot = lane / LPR;
+  // word w of run slot s of this wave's round at s_mask[s * SW + w]; this
+  // lane's piece is s_mask[2 lane], s_mask[2 lane + 1]
+  uint64_t *const s_mask = reinterpret_cast<uint64_t *>(T.scratch) + wave * 128;
 
   acquire_device();
   uint64_t tile;
@@ -228,33 +233,46 @@ __global__ __launch_bounds__(WG) void insert_wide_kernel(const uint8_t *__restri
       if (heads) carry = s0 + 63 - __clzll((long long)heads);
       const int nruns = __popcll(tails);
       for (int r0 = 0; r0 < nruns; r0 += RPR) {
-        const int j = r0 + lane / LPR;
+        const int j = r0 + slot;
+        // The buffer words pass between the lanes of the wave, so every
+        // access is atomic, and a wavefront-scope fence orders the other
+        // lanes' ORs before this lane's reads (a plain read after a plain
+        // clear could be taken as still zero for a lane that ORed nothing).
+        __hip_atomic_store(&s_mask[2 * lane], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __hip_atomic_store(&s_mask[2 * lane + 1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        uint64_t *line = nullptr;
+        uint64_t o0 = 0, o1 = 0;
         if (j < nruns) {
           const uint32_t rsh = s_run_shard[wave][j];
           const uint32_t span = s_run_span[wave][j];
           const int a = (int)(span & 0xFFFFu);
           const int b = (int)(span >> 16);
-          uint64_t *line = words + (uint64_t)rsh * SW + 2 * p;
-          uint64_t o0 = 0, o1 = 0;
+          line = words + (uint64_t)rsh * SW + 2 * p;
           if constexpr (MODE == kWideStore) {
             const uint4 piece = *reinterpret_cast<const uint4 *>(line);
             o0 = ((uint64_t)piece.y << 32) | piece.x;
             o1 = ((uint64_t)piece.w << 32) | piece.z;
           }
-          uint64_t m[2] = {0, 0};
-          for (int x = a; x <= b + Z; ++x) {
+          uint64_t *run_words = s_mask + slot * SW;
+          for (int x = a + p; x <= b + Z; x += LPR) {
             const wide_pack_t<H> pk = T.bits[x];
 #pragma unroll
-            for (int i = 0; i < H / 4; ++i) {
-#pragma unroll
-              for (int u = 0; u < 2; ++u) {
-                const uint32_t byte = addr_byte<H>(pk, 4 * i + u + e);
-                uint64_t one = 1ull << (byte & 63u);
-                if constexpr (SW > 4) one = (byte >> 6) == grp ? one : 0ull;
-                m[u] |= one;
-              }
+            for (int t = 0; t < H; ++t) {
+              const uint32_t byte = addr_byte<H>(pk, t);
+              const int w = (t & 3) + 4 * (int)(byte >> 6);
+              __hip_atomic_fetch_or(run_words + w, 1ull << (byte & 63u), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
           }
+        }
+        // (a wave's LDS operations take effect in order) the piece now holds
+        // the bits of every s-mer of the run
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (j < nruns) {
+          const uint64_t m[2] = {
+              __hip_atomic_load(&s_mask[2 * lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT),
+              __hip_atomic_load(&s_mask[2 * lane + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)};
           if constexpr (MODE == kWideStore) {
             // coherent store of the piece (see store_pair_coherent)
             if ((o0 | m[0]) != o0 || (o1 | m[1]) != o1) store_pair_coherent(line, o0 | m[0], o1 | m[1]);
