@@ -1023,8 +1023,8 @@ def measure(args, name, with_cpu):
     ins_launches = 1 if settings["insert_mode"] == 1 else 2
     if family == "wide-shard":
         q_kernel = "query_wide_kernel<31,28,16,4,%d,%d>" % (S, tile_q)
-        ins_kernels = ("insert_wide_kernel<31,28,16,4,%d,%d> store pass + query_wide_kernel<31,28,16,4,%d,%d> repair "
-                       "walk" % (S, tile_i, S, tile_i), "insert_wide_kernel<31,28,16,4,%d,%d> (atomic)" % (S, tile_i))
+        ins_kernels = ("insert_wide_kernel<31,28,16,4,%d,%d> store pass + repair walk (two launches)" % (S, tile_i),
+                       "insert_wide_kernel<31,28,16,4,%d,%d> (atomic)" % (S, tile_i))
     elif family == "run-time parameter":
         q_kernel = "query_param_kernel<%d,%d>" % (S, tile_q)
         ins_kernels = ("insert_param_kernel<%d,%d> store pass + query_param_kernel<%d,%d> repair walk"

@@ -20,12 +20,12 @@
 //     covers whole lines (the paper's leader load and shard sharing,
 //     Algorithms 1 and 2, with the line split across lanes instead of
 //     broadcast from one).
-// Insert: the lanes of a run's line each OR into their piece the bits of the
-//   run's s-mers that fall in their two words (computed from the LDS
-//   addresses), then write it back if it changed (a read-modify-write whose
-//   store writes through to the device's coherence point; a second launch,
-//   the query kernel with REPAIR, atomically restores any bit a concurrent
-//   write dropped) or, in atomic mode, issue 64-bit atomic ORs.  A run that
+// Insert: the lanes of a run's line OR the run's s-mer bits into an LDS copy
+//   of the line, then each ORs its two words into its piece and writes it
+//   back if it changed (a read-modify-write whose store writes through to the
+//   device's coherence point; a second launch of the same kernel reads each
+//   run's line again and atomically ORs in any bit a concurrent write
+//   dropped) or, in atomic mode, issues 64-bit atomic ORs.  A run that
 //   continues into the wave's next step is written once.
 // Query: the lanes of a run stage its line in LDS; each k-mer lane then tests
 //   its (k-s+1)*H bits there (Algorithm 2, Contains).
@@ -161,7 +161,11 @@ __device__ __forceinline__ void wide_phase1(WideTile<K, S, H, LP, WG, SCR> &T, c
   __syncthreads();
 }
 
-enum WideInsertMode : int { kWideAtomic = 0, kWideStore = 1 };
+// How a run's bits reach its shard: 64-bit atomic ORs; a read-modify-write
+// with a coherent store (the store pass of the two-pass insert); or, after
+// the store pass, a read and an atomic OR of only the bits still missing (the
+// repair walk, one check per run instead of per k-mer).
+enum WideInsertMode : int { kWideAtomic = 0, kWideStore = 1, kWideRepair = 2 };
 
 // ---------------------------------------------------------------------------
 // Insert.  Lane (run j, piece p) of a round owns words 2p and 2p+1 of run j's
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(WG) void insert_wide_kernel(const uint8_t *__restri
           const int a = (int)(span & 0xFFFFu);
           const int b = (int)(span >> 16);
           line = words + (uint64_t)rsh * SW + 2 * p;
-          if constexpr (MODE == kWideStore) {
+          if constexpr (MODE != kWideAtomic) {
             const uint4 piece = *reinterpret_cast<const uint4 *>(line);
             o0 = ((uint64_t)piece.y << 32) | piece.x;
             o1 = ((uint64_t)piece.w << 32) | piece.z;
@@ -276,6 +280,10 @@ __global__ __launch_bounds__(WG) void insert_wide_kernel(const uint8_t *__restri
           if constexpr (MODE == kWideStore) {
             // coherent store of the piece (see store_pair_coherent)
             if ((o0 | m[0]) != o0 || (o1 | m[1]) != o1) store_pair_coherent(line, o0 | m[0], o1 | m[1]);
+          } else if constexpr (MODE == kWideRepair) {
+            // the bits a racing store dropped
+            if (m[0] & ~o0) atomic_or64(line, m[0] & ~o0);
+            if (m[1] & ~o1) atomic_or64(line + 1, m[1] & ~o1);
           } else {
             if (m[0]) atomic_or64(line, m[0]);
             if (m[1]) atomic_or64(line + 1, m[1]);
@@ -287,16 +295,16 @@ __global__ __launch_bounds__(WG) void insert_wide_kernel(const uint8_t *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Query (and the insert's repair walk).  Runs restart at every step; the
+// Query.  Runs restart at every step; the
 // lines of up to PASS runs of the step are staged in LDS at once.  A line is
 // stored sector-major: dword (t mod 4) * SW/2 + 2 * group + half holds half
 // `half` of word (t mod 4) + 4 * group, so the dword of an address byte b of
 // hash index t is (t mod 4) * SW/2 + (b >> 5) and its bit is b & 31.
 // ---------------------------------------------------------------------------
-template <int K, int S, int M, int H, int SW, int LP, int WG, bool REPAIR>
+template <int K, int S, int M, int H, int SW, int LP, int WG>
 __global__ __launch_bounds__(WG) void query_wide_kernel(const uint8_t *__restrict__ seq, uint64_t len,
                                                         const uint32_t *__restrict__ starts, int aligned16,
-                                                        typename std::conditional<REPAIR, uint64_t, const uint64_t>::type *words,
+                                                        const uint64_t *__restrict__ words,
                                                         uint32_t shard_mask, uint8_t *__restrict__ out,
                                                         uint64_t n_out, TileQueue tq) {
   constexpr int Z = K - S;
@@ -372,25 +380,14 @@ __global__ __launch_bounds__(WG) void query_wide_kernel(const uint8_t *__restric
             for (int t = 0; t < H; ++t) {
               const uint32_t byte = addr_byte<H>(pk, t);
               const uint32_t d = L[(t & 3) * HALF + (byte >> 5)];
-              const uint32_t hit = (d >> (byte & 31u)) & 1u;
-              if constexpr (REPAIR) {
-                if (!hit) {
-                  // restore a bit a racing insert store dropped
-                  const int w = (t & 3) + 4 * (int)(byte >> 6);
-                  atomic_or64(words + (uint64_t)sh * SW + w, 1ull << (byte & 63u));
-                }
-              } else {
-                acc &= hit;
-              }
+              acc &= (d >> (byte & 31u)) & 1u;
             }
           }
           ok = acc;
         }
       }
-      if constexpr (!REPAIR) {
-        const uint64_t pos = base + (uint64_t)q;
-        if (pos < n_out) out[pos] = (uint8_t)(v ? ok : 0u);
-      }
+      const uint64_t pos = base + (uint64_t)q;
+      if (pos < n_out) out[pos] = (uint8_t)(v ? ok : 0u);
     }
   }
 }
@@ -412,8 +409,8 @@ hipError_t insert_wide(uint64_t *words, uint32_t shard_mask, const SeqArgs &a, i
   }
   SBF_LAUNCH_TILES((insert_wide_kernel<K, S, M, H, SW, LP, kWideWG, kWideStore>), kWideWG, ntiles, 0, a.seq, a.len,
                    a.starts, aligned, words, shard_mask);
-  SBF_LAUNCH_TILES((query_wide_kernel<K, S, M, H, SW, LP, kWideWG, true>), kWideWG, ntiles, 1, a.seq, a.len,
-                   a.starts, aligned, words, shard_mask, (uint8_t *)nullptr, nk);
+  SBF_LAUNCH_TILES((insert_wide_kernel<K, S, M, H, SW, LP, kWideWG, kWideRepair>), kWideWG, ntiles, 1, a.seq,
+                   a.len, a.starts, aligned, words, shard_mask);
   return hipSuccess;
 }
 
@@ -424,7 +421,7 @@ hipError_t query_wide(const uint64_t *words, uint32_t shard_mask, const SeqArgs 
   if (a.packed) return hipErrorInvalidValue;  // answers as bytes only
   const uint64_t tile = (uint64_t)LP * kWideWG;
   const int aligned = ((uintptr_t)a.seq & 15u) == 0;
-  SBF_LAUNCH_TILES((query_wide_kernel<K, S, M, H, SW, LP, kWideWG, false>), kWideWG, (a.n_out + tile - 1) / tile,
+  SBF_LAUNCH_TILES((query_wide_kernel<K, S, M, H, SW, LP, kWideWG>), kWideWG, (a.n_out + tile - 1) / tile,
                    2, a.seq, a.len, a.starts, aligned, words, shard_mask, a.out, a.n_out);
   return hipSuccess;
 }
