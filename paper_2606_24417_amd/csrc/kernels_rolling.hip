@@ -109,7 +109,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
       {
         uint64_t hb[W];
 #pragma unroll
-        for (int i = 0; i < W; ++i) hb[i] = mmer_hash<M>(a, i);
+        for (int i = 0; i < W; ++i) hb[i] = mmer_hash<M, true>(a, i);
         suf[W - 1] = hb[W - 1];
 #pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
             if (i == 0) {
               mu = suf[0];
             } else {
-              hb[i - 1] = mmer_hash<M>(a, r + W - 1);
+              hb[i - 1] = mmer_hash<M, true>(a, r + W - 1);
               pre = umin64(pre, hb[i - 1]);
               mu = umin64(suf[i], pre);
             }
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(WG) void insert_rolling_kernel(const uint8_t *__res
           }
         }
         if ((q + 1) * W < L) {
-          hb[W - 1] = mmer_hash<M>(a, (q + 1) * W + W - 1);
+          hb[W - 1] = mmer_hash<M, true>(a, (q + 1) * W + W - 1);
           suf[W - 1] = hb[W - 1];
 #pragma unroll
           for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
       {
         uint64_t hb[W];
 #pragma unroll
-        for (int i = 0; i < W; ++i) hb[i] = mmer_hash<M>(a, i);
+        for (int i = 0; i < W; ++i) hb[i] = mmer_hash<M, true>(a, i);
         suf[W - 1] = hb[W - 1];
 #pragma unroll
         for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
             if (i == 0) {
               mu = suf[0];
             } else {
-              hb[i - 1] = mmer_hash<M>(a, r + W - 1);
+              hb[i - 1] = mmer_hash<M, true>(a, r + W - 1);
               pre = umin64(pre, hb[i - 1]);
               mu = umin64(suf[i], pre);
             }
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(WG) void query_rolling_kernel(const uint8_t *__rest
           }
         }
         if ((q + 1) * W < L) {
-          hb[W - 1] = mmer_hash<M>(a, (q + 1) * W + W - 1);
+          hb[W - 1] = mmer_hash<M, true>(a, (q + 1) * W + W - 1);
           suf[W - 1] = hb[W - 1];
 #pragma unroll
           for (int i = W - 2; i >= 0; --i) suf[i] = umin64(hb[i], suf[i + 1]);
@@ -403,10 +403,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
 #pragma unroll
     for (int i = 0; i < NGW; ++i) a[i] = s_codes[g0 + i];
     const uint64_t kv = lane_kmer_valid<K, L>(s_vb, g0);
-    // Bit r of ans: k-mer r found (the validity mask is applied at the end).
-    uint32_t ans[(L + 31) / 32];
+    // lost[i]: one bit per k-mer 32i .. 32i+31, set where some bit of the
+    // k-mer is missing from its shard, shifted in from the right (k-mer 32i+j
+    // ends at bit n-1-j of the word's n k-mers); reversed, inverted and
+    // masked by validity at the end into ans.
+    uint32_t lost[(L + 31) / 32];
 #pragma unroll
-    for (int i = 0; i < (L + 31) / 32; ++i) ans[i] = 0;
+    for (int i = 0; i < (L + 31) / 32; ++i) lost[i] = 0;
 
     if (kv != 0) {
       uint64_t oh[L + Z][4];
@@ -417,6 +420,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
       uint32_t sh_at[L];       // shard of k-mer r (repair)
       uint64_t got[4];         // shard words of the last tested k-mer
       uint32_t prev_sh = 0;
+      // 32 bytes per shard, as an operand the compiler cannot fold: the
+      // shard's address is then one 32x32+64 multiply-add instead of a 64-bit
+      // shift and add
+      uint32_t shard_bytes = 32;
+      asm("" : "+s"(shard_bytes));
 #pragma unroll
       for (int j = 0; j < Z; ++j) smer_onehots<H>(smer_hash(smer_at<S>(a, j)), oh[j]);
       if constexpr (Z == 3) {
@@ -428,11 +436,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
       const int t = threadIdx.x;
       {
         // suffix minima of block 0
-        uint64_t m = mmer_hash<M>(a, W - 1);
+        uint64_t m = mmer_hash<M, true>(a, W - 1);
         s_vh[W - 1][t] = m;
 #pragma unroll
         for (int i = W - 2; i >= 0; --i) {
-          m = umin64(mmer_hash<M>(a, i), m);
+          m = umin64(mmer_hash<M, true>(a, i), m);
           s_vh[i][t] = m;
         }
       }
@@ -473,7 +481,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
             }
           }
         } else {
-          if (miss == 0) ans[r >> 5] |= 1u << (r & 31);
+          // lost = 2 lost + (miss != 0): a compare and an add with carry (the
+          // compiler's form, a select of the bit and an OR, takes a third
+          // instruction and often a fourth to move the bit's constant)
+          asm("v_cmp_ne_u32_e32 vcc, 0, %1\n\tv_addc_co_u32_e32 %0, vcc, %0, %0, vcc"
+              : "+v"(lost[r >> 5])
+              : "v"(miss)
+              : "vcc");
         }
       };
 #pragma unroll
@@ -487,7 +501,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
             if (i == 0) {
               mu = s_vh[0][t];
             } else {
-              const uint64_t h = mmer_hash<M>(a, r + W - 1);  // position i-1 of block q+1
+              const uint64_t h = mmer_hash<M, true>(a, r + W - 1);  // position i-1 of block q+1
               pre = umin64(pre, h);
               mu = umin64(s_vh[i][t], pre);
               s_vh[i - 1][t] = h;  // slot i-1 was last read at step i-1
@@ -499,8 +513,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
             const uint32_t sh = (uint32_t)mu & shard_mask;
             const bool fresh = r == 0 || sh != prev_sh;
             prev_sh = sh;
-            const uint32_t lsh = fresh ? sh : 0u;
-            const uint4 *p = reinterpret_cast<const uint4 *>(words + 4ull * (uint64_t)lsh);
+            // the select on the 32-bit index (the asm operand keeps the
+            // compiler from moving it past the widening to a byte offset,
+            // where it takes a 64-bit shift and two selects)
+            uint32_t lsh = fresh ? sh : 0u;
+            asm("" : "+v"(lsh));
+            const uint4 *p = reinterpret_cast<const uint4 *>(reinterpret_cast<const uint8_t *>(words) +
+                                                             (uint64_t)lsh * (uint64_t)shard_bytes);
             const uint4 lo = p[0], hi = p[1];
             ldw[r][0] = ((uint64_t)lo.y << 32) | lo.x;
             ldw[r][1] = ((uint64_t)lo.w << 32) | lo.z;
@@ -528,7 +547,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
         }
         if ((q + 1) * W < L) {
           // suffix minima of block q+1, in place over its hashes
-          uint64_t m = mmer_hash<M>(a, (q + 1) * W + W - 1);
+          uint64_t m = mmer_hash<M, true>(a, (q + 1) * W + W - 1);
           s_vh[W - 1][t] = m;
 #pragma unroll
           for (int i = W - 2; i >= 0; --i) {
@@ -541,8 +560,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4))) void qu
       for (int r = L - D; r < L; ++r) test(r);
     }
     if constexpr (REPAIR) continue;  // no answers
+    uint32_t ans[(L + 31) / 32];
 #pragma unroll
-    for (int i = 0; i < (L + 31) / 32; ++i) ans[i] &= (uint32_t)(kv >> (32 * i));
+    for (int i = 0; i < (L + 31) / 32; ++i) {
+      constexpr int kFull = 32;
+      const int n = L - kFull * i < kFull ? L - kFull * i : kFull;
+      ans[i] = ~(__builtin_bitreverse32(lost[i]) >> (kFull - n)) & (uint32_t)(kv >> (kFull * i));
+    }
     if (out_packed) {
       // One answer bit per k-mer: the lane's L bits start at bit base +
       // lane_off, a multiple of 16, so they are L/16 aligned 16-bit words;

@@ -26,6 +26,18 @@ __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < 
 
 // h_M of a (zero-extended) m-mer of at most 16 bases.
 __device__ __forceinline__ uint64_t minimizer_hash32(uint32_t y) { return (uint64_t)y * kMinimizerMul; }
+// The same low 64 bits of y * kMinimizerMul as one 32x32->64 multiply plus
+// the high word's 32-bit partial product.  The empty asm operand keeps that
+// partial product a plain multiply and add: fused into a second 64-bit
+// multiply-add it needs its addend in a register pair, which costs two moves
+// per hash.  Measured faster in the lane kernels and slower in the wide-shard
+// kernels, whose m-mer loop the compiler schedules better in the fused form.
+__device__ __forceinline__ uint64_t minimizer_hash32_split(uint32_t y) {
+  const uint64_t p = (uint64_t)y * (uint32_t)kMinimizerMul;
+  uint32_t t = y * (uint32_t)(kMinimizerMul >> 32);
+  asm("" : "+v"(t));
+  return ((uint64_t)((uint32_t)(p >> 32) + t) << 32) | (uint32_t)p;
+}
 __device__ __forceinline__ uint64_t minimizer_hash(uint64_t y) { return y * kMinimizerMul; }
 
 // h_S: xorshift 30, multiply, xorshift 31.

@@ -61,12 +61,14 @@ __device__ __forceinline__ bool next_tile(const TileQueue &q, uint32_t *s_slot, 
 }
 
 // Minimizer hash h_M of the m-mer at window position j (2m-bit value, first
-// base most significant; m <= 16 fits 32 bits).
-template <int M>
+// base most significant; m <= 16 fits 32 bits).  SPLIT selects the split
+// 32-bit multiply for m <= 16 (same value).
+template <int M, bool SPLIT = false>
 __device__ __forceinline__ uint64_t mmer_hash(const uint32_t *a, int j) {
   static_assert(M >= 1 && M <= 32, "m-mers fit 64 bits");
   if constexpr (M <= 16) {
-    return minimizer_hash32(win32(a, j) >> (32 - 2 * M));
+    const uint32_t y = win32(a, j) >> (32 - 2 * M);
+    return SPLIT ? minimizer_hash32_split(y) : minimizer_hash32(y);
   } else {
     const uint32_t hi = win32(a, j) >> (64 - 2 * M);
     const uint32_t lo = win32(a, j + M - 16);
