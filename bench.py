@@ -43,8 +43,12 @@ KERNEL_SOURCES = ["paper_2606_24417_amd/csrc/kernels_rolling.hip", "paper_2606_2
 
 def kernel_source_hash() -> str:
     """Hash of the kernel sources with comments and whitespace removed, so that
-    stored counters stay valid across comment-only edits."""
+    stored counters stay valid across comment-only edits, and of the compiler
+    flags they are built with (a flag can change the code as much as an
+    edit)."""
     import re
+
+    from paper_2606_24417_amd import build as B
 
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -53,6 +57,7 @@ def kernel_source_hash() -> str:
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
+        h.update(" ".join(B.HIPCC_FLAGS + B.SOURCE_FLAGS.get(os.path.basename(p), [])).encode())
     return h.hexdigest()[:16]
 
 

@@ -26,6 +26,14 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
+# Per-source flags.  The lane kernels fully unroll their walk of 32, 48 or 64
+# k-mers so that every per-k-mer array is indexed by constants and lives in
+# registers; the larger instantiations (m = 18, whose van Herk block of 14
+# needs four blocks for 48 k-mers; the 64-k-mer insert) exceed the default
+# size budget of an unroll pragma, and the walk's arrays then go to scratch
+# memory (a few hundred scratch accesses per k-mer step, 5-20x slower).
+SOURCE_FLAGS = {"kernels_rolling.hip": ["-mllvm", "-pragma-unroll-threshold=65536"]}
+
 
 def hipcc() -> str:
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
@@ -56,8 +64,8 @@ def _compile(out: str, sources, verbose: bool) -> str:
     flags = [f for f in HIPCC_FLAGS if f != "-shared"]
 
     def one(i):
-        _run([hipcc()] + flags + inc + ["-c", "-o", objs[i], os.path.join(CSRC, sources[i])], verbose,
-             os.path.basename(out))
+        _run([hipcc()] + flags + SOURCE_FLAGS.get(sources[i], []) + inc +
+             ["-c", "-o", objs[i], os.path.join(CSRC, sources[i])], verbose, os.path.basename(out))
 
     try:
         workers = max(1, min(len(sources), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1)))

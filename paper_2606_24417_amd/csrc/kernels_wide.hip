@@ -61,12 +61,6 @@ __device__ __forceinline__ wide_pack_t<H> wide_addresses(uint64_t g) {
   return p;
 }
 
-// Byte t of a packed address set.
-template <int H>
-__device__ __forceinline__ uint32_t addr_byte(wide_pack_t<H> pk, int t) {
-  return (uint32_t)(pk >> (8 * t)) & 0xFFu;
-}
-
 // LDS of one tile: the staged sequence, then per k-mer its shard and
 // validity and per s-mer its packed addresses.  The staged sequence is only
 // read in phase 1, so phase 2 may reuse its bytes and SCR more (scratch).
@@ -262,11 +256,22 @@ __global__ __launch_bounds__(WG) void insert_wide_kernel(const uint8_t *__restri
           for (int x = a + p; x <= b + Z; x += LPR) {
             const wide_pack_t<H> pk = T.bits[x];
 #pragma unroll
-            for (int t = 0; t < H; ++t) {
-              const uint32_t byte = addr_byte<H>(pk, t);
-              const int w = (t & 3) + 4 * (int)(byte >> 6);
-              __hip_atomic_fetch_or(run_words + w, 1ull << (byte & 63u), __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_WAVEFRONT);
+            for (int h = 0; h < (H + 3) / 4; ++h) {
+              // byte u of o4: the offset in the run's line of word
+              // (u mod 4) + 4 * group of address u (8 bytes per word, 32 per
+              // group), one shift, mask and add for four addresses (the asm
+              // operand keeps the compiler from splitting them again)
+              constexpr uint32_t kWords = 8u << 8 | 16u << 16 | 24u << 24;
+              const uint32_t p4 = (uint32_t)(pk >> (32 * h));
+              uint32_t o4 = ((p4 >> 1) & 0x60606060u) + kWords;
+              asm("" : "+v"(o4));
+#pragma unroll
+              for (int u = 0; u < 4 && 4 * h + u < H; ++u) {
+                uint64_t *wp = reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(run_words) +
+                                                            ((o4 >> (8 * u)) & 0xFFu));
+                __hip_atomic_fetch_or(wp, 1ull << ((p4 >> (8 * u)) & 63u), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
+              }
             }
           }
         }
@@ -371,16 +376,28 @@ __global__ __launch_bounds__(WG) void query_wide_kernel(const uint8_t *__restric
           }
         }
         if (v && ri >= r0 && ri < r0 + PASS) {
-          const uint32_t *L = reinterpret_cast<const uint32_t *>(s_line[wave][ri - r0]);
+          const uint8_t *Lb = reinterpret_cast<const uint8_t *>(s_line[wave][ri - r0]);
           uint32_t acc = 1;
 #pragma unroll
           for (int o = 0; o <= Z; ++o) {
             const wide_pack_t<H> pk = T.bits[q + o];
 #pragma unroll
-            for (int t = 0; t < H; ++t) {
-              const uint32_t byte = addr_byte<H>(pk, t);
-              const uint32_t d = L[(t & 3) * HALF + (byte >> 5)];
-              acc &= (d >> (byte & 31u)) & 1u;
+            for (int h = 0; h < (H + 3) / 4; ++h) {
+              // four addresses at once: byte u of o4 is the offset in the
+              // staged line of the dword holding address u (its sector's
+              // u * HALF dwords plus (address >> 5)), one shift, mask and
+              // add for the four; each read is then the line base plus one
+              // byte of o4 (the asm operand keeps the compiler from splitting
+              // the shared computation back into four)
+              constexpr uint32_t kSectors = (4u * HALF) << 8 | (8u * HALF) << 16 | (12u * HALF) << 24;
+              const uint32_t p4 = (uint32_t)(pk >> (32 * h));
+              uint32_t o4 = ((p4 >> 3) & 0x1C1C1C1Cu) + kSectors;
+              asm("" : "+v"(o4));
+#pragma unroll
+              for (int u = 0; u < 4 && 4 * h + u < H; ++u) {
+                const uint32_t d = *reinterpret_cast<const uint32_t *>(Lb + ((o4 >> (8 * u)) & 0xFFu));
+                acc &= (d >> ((p4 >> (8 * u)) & 31u)) & 1u;
+              }
             }
           }
           ok = acc;
