@@ -211,14 +211,16 @@ int sbf_get_variant(const sbf_filter *f);
  * lanes of them; with about 8.5 k-mers per super-k-mer, Section "Minimizers
  * and Super-k-mers", that is the tile's super-k-mer count times 8.5 / 256).
  * 0 selects the family's default.  Compiled lengths:
- *   4-word lane kernels, (31,28,16,4) only: insert 32 (default) or 64 k-mers
- *     per lane for the store pass; query 48 (default) or 32, which the
- *     insert's repair walk uses as well;
+ *   4-word lane kernels, (31,28,16,4) only: insert 64 or 32 k-mers per lane
+ *     for the store pass (default: 64 for an insert call of at least 2^24
+ *     k-mers, 32 below; other sets: 32 only); query 48 (default) or 32,
+ *     which the insert's repair walk uses as well;
  *   wide-shard kernels: 16 (default) or 32 for insert and query;
  *   run-time parameter kernels: 8 (default) or 16 for insert and query.
  * Other values (and any value for the generic kernels) return SBF_E_INVAL.
  * The result does not depend on the tile size.  sbf_get_tile reads the
- * effective lengths back (0 for the generic kernels; pointers may be NULL). */
+ * effective lengths back (0 for the generic kernels; pointers may be NULL;
+ * the lane kernels' size-dependent insert default reads as 64). */
 int sbf_set_tile(sbf_filter *f, uint32_t insert_kmers_per_lane, uint32_t query_kmers_per_lane);
 int sbf_get_tile(const sbf_filter *f, uint32_t *insert_kmers_per_lane, uint32_t *query_kmers_per_lane);
 

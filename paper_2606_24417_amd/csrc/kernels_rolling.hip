@@ -615,11 +615,16 @@ constexpr int kQueryLaneL = 48;
 constexpr int kQueryLaneWG = 256;
 constexpr int kQueryLaneD = 1;
 
-// Compiled lane lengths: the insert's store pass walks 32 (default) or 64
-// k-mers per lane, the query and the insert's repair walk 48 (default) or 32;
-// the non-default lengths exist for the paper's default parameter set only.
+// Compiled lane lengths: the insert's store pass walks 32 k-mers per lane,
+// and for the paper's default parameter set also 64, its default there for
+// inserts of at least kLongInsertKmers k-mers (1.7% faster out of cache, the
+// walk held in registers; a smaller insert has too few 16384-k-mer tiles for
+// the 1024 resident workgroups and keeps 32); the query and the insert's
+// repair walk 48 (default) or 32.  The second lengths exist for the paper's
+// default parameter set only.
 template <int K, int S, int M, int H>
 constexpr bool lane_len_variants() { return K == 31 && S == 28 && M == 16 && H == 4; }
+constexpr uint64_t kLongInsertKmers = 1ull << 24;
 
 template <int K, int S, int M, int H, int QL>
 hipError_t query_lane_launch(const uint64_t *words, uint32_t shard_mask, const SeqArgs &a, const LaunchShape &ls,
@@ -663,7 +668,7 @@ hipError_t insert_rolling(uint64_t *words, uint32_t shard_mask, const SeqArgs &a
   const int aligned = ((uintptr_t)a.seq & 15u) == 0;
   hipError_t e;
   if constexpr (lane_len_variants<K, S, M, H>()) {
-    if (ls.insert_lane_len == 64)
+    if (ls.insert_lane_len == 64 || (ls.insert_lane_len == 0 && nk >= kLongInsertKmers))
       e = store_launch<K, S, M, H, 64>(words, shard_mask, a, nk, mode, ls, st, aligned);
     else
       e = store_launch<K, S, M, H, kInsertL>(words, shard_mask, a, nk, mode, ls, st, aligned);

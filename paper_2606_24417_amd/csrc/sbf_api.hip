@@ -176,7 +176,11 @@ bool lane_len_ok(const sbf_filter *f, uint32_t n, bool insert) {
 uint32_t lane_len_effective(const sbf_filter *f, uint32_t n, bool insert) {
   if (n) return n;
   switch (family(f)) {
-    case kLaneFamily: return insert ? 32 : 48;
+    case kLaneFamily: {
+      const Geometry &g = f->g;
+      const bool variants = g.k == 31 && g.s == 28 && g.m == 16 && g.H == 4;
+      return insert ? (variants ? 64 : 32) : 48;
+    }
     case kWideFamily: return 16;
     case kParamFamily: return 8;
     default: return 0;

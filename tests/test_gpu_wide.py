@@ -149,7 +149,7 @@ def test_auto_variant_picks_wide_kernels_for_wide_shards():
             f.set_tile(16, 16)
         f.close()
     f = Filter(31, 28, 16, 4, 1 << 20)
-    assert f.variant == VARIANT_ROLLING and f.get_tile() == (32, 48)
+    assert f.variant == VARIANT_ROLLING and f.get_tile() == (64, 48)
     f.set_tile(64, 32)
     assert f.get_tile() == (64, 32)
     with pytest.raises(SBFError):
